@@ -1,0 +1,144 @@
+/*
+ * hiz: error-bounded lossy compression of FP32 3-D fields on AMD MI355X
+ * (gfx950), after the interpolation compressor cuSZ-Hi (arXiv 2507.11165).
+ *
+ * The library implements the problem of Sec. 3.1, Eq. "general": a compressor
+ * Cmp and decompressor Dec with Z = Cmp(X), X' = Dec(Z) and
+ * max_i |x_i - x'_i| <= eps for every element. The lossy stage is the anchor-
+ * based, four-level spline interpolation predictor over 17^3 blocks
+ * (Sec. 5.1.1-5.1.3) fused with linear-scaling quantization to one-byte codes
+ * (Sec. 5.2.1); the lossless stage is Huffman coding of the codes (Sec. 5.2.2).
+ *
+ * Conventions shared by every entry point:
+ *  - Fields are FP32, C-contiguous, shape dims = {dx, dy, dz}; element
+ *    (x, y, z) is at linear index (x*dy + y)*dz + z (z fastest).
+ *  - Pointers named d_* are device pointers on the context's device; the
+ *    caller owns them and the library never frees or retains them past the
+ *    call. Buffers passed as d_field must be 4-byte aligned, streams 16-byte
+ *    aligned.
+ *  - All device work is enqueued on the caller's HIP stream `stream`
+ *    (0 = the default stream). Calls that return sizes or statuses
+ *    synchronize that stream before returning.
+ *  - No call throws; failures return a nonzero hiz_status and leave a message
+ *    for hiz_last_error. Output buffers are undefined after a failure.
+ *  - A context is not thread-safe: use one context per host thread.
+ */
+#ifndef HIZ_H
+#define HIZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hiz_ctx hiz_ctx;
+typedef struct ihipStream_t *hiz_stream_t; /* == hipStream_t */
+
+typedef enum {
+    HIZ_OK = 0,
+    HIZ_ERR_ARG = 1,       /* invalid argument: zero dims, eb <= 0, NULL, bad params */
+    HIZ_ERR_NONFINITE = 2, /* the field holds NaN or Inf */
+    HIZ_ERR_BUFSZ = 3,     /* output capacity too small; *out_size holds the size needed */
+    HIZ_ERR_CORRUPT = 4,   /* stream fails a structural check */
+    HIZ_ERR_NOMEM = 5,     /* device or pinned allocation failed */
+    HIZ_ERR_HIP = 6        /* a HIP runtime call failed */
+} hiz_status;
+
+/* Error-bound modes (Sec. 3.1; Sec. 6.1.4: the paper's bounds are relative
+ * to the value range, eps = eb * (max - min)). */
+typedef enum { HIZ_ABS = 0, HIZ_REL = 1 } hiz_eb_mode;
+
+/* Interpolation choices of one level (Sec. 5.1.2). */
+enum { HIZ_SPLINE_LINEAR = 0, HIZ_SPLINE_CUBIC = 1 };
+enum { HIZ_SCHEME_MD = 0, HIZ_SCHEME_SEQ = 1 };
+/* SEQ dimension orders: 0 (x,y,z) 1 (x,z,y) 2 (y,x,z) 3 (y,z,x) 4 (z,x,y) 5 (z,y,x). */
+
+typedef struct {
+    /* 1 (default): pick each level's spline and scheme with the sampled-block
+     * tuner of Sec. 5.1.3; 0: use `level_cfg`. */
+    int tune;
+    /* Per level, strides 8, 4, 2, 1: {spline, scheme, order}. */
+    uint8_t level_cfg[4][3];
+    /* Huffman chunk length in symbols: a power of two in [256, 65536];
+     * 0 = the library's size-keyed default. Recorded in the stream. */
+    uint32_t chunk;
+    /* Cells along z per GPU tile (1, 2 or 4); 0 = default. Does not change the
+     * output. */
+    uint32_t tile_z;
+} hiz_params;
+
+/* Header view of a stream (host-side parse; see hiz_inspect). */
+typedef struct {
+    uint64_t dims[3];
+    int mode;
+    double eb;
+    float eps;          /* absolute bound used; every |x - x'| <= eps */
+    float vmin, vmax;   /* exact min and max of the input */
+    int constant;       /* 1: constant field stored as one value */
+    uint8_t level_cfg[4][3];
+    uint32_t chunk;
+    uint64_t n_outliers;
+    uint64_t n_chunks;
+    uint64_t payload_words;
+    uint64_t total_bytes;
+} hiz_info;
+
+/* Create a context on HIP device `device`. `workspace_bytes` reserves device
+ * scratch up front (0 = grow on demand). The context owns its workspace, code
+ * buffers and tables; release it with hiz_destroy. */
+hiz_status hiz_create(int device, size_t workspace_bytes, hiz_ctx **out);
+void hiz_destroy(hiz_ctx *ctx);
+
+/* Message describing the last failure on this context ("" if none). The
+ * string lives until the next call on the context. */
+const char *hiz_last_error(const hiz_ctx *ctx);
+
+/* Largest stream any field of these dims can produce (every point an
+ * outlier and 32-bit codewords); 0 if dims are invalid. */
+uint64_t hiz_compress_bound(const uint64_t dims[3]);
+
+/* Z = Cmp(X) (Sec. 3.1). Reads the field d_field (dims[0]*dims[1]*dims[2]
+ * floats), writes the stream to d_out (capacity out_cap bytes) and its size
+ * to *out_size (host memory) after synchronizing `stream`.
+ * mode HIZ_REL: eps = eb * (max - min) rounded down to FP32; a field with
+ * max == min is stored as a constant stream. params may be NULL (defaults).
+ * Errors: HIZ_ERR_ARG, HIZ_ERR_NONFINITE, HIZ_ERR_BUFSZ (*out_size = size
+ * needed), HIZ_ERR_NOMEM, HIZ_ERR_HIP. */
+hiz_status hiz_compress(hiz_ctx *ctx, const float *d_field, const uint64_t dims[3],
+                        hiz_eb_mode mode, double eb, const hiz_params *params,
+                        void *d_out, uint64_t out_cap, uint64_t *out_size,
+                        hiz_stream_t stream);
+
+/* X' = Dec(Z) (Sec. 3.1). Reads the stream d_in (in_size bytes), writes
+ * dims[0]*dims[1]*dims[2] floats to d_field (capacity field_cap elements).
+ * If dims_out is not NULL it receives the field's dims. Synchronizes `stream`.
+ * Errors: HIZ_ERR_CORRUPT, HIZ_ERR_BUFSZ (field_cap too small), HIZ_ERR_ARG,
+ * HIZ_ERR_NOMEM, HIZ_ERR_HIP. */
+hiz_status hiz_decompress(hiz_ctx *ctx, const void *d_in, uint64_t in_size,
+                          float *d_field, uint64_t field_cap, uint64_t dims_out[3],
+                          hiz_stream_t stream);
+
+/* Parse the header of a stream held in HOST memory (h_stream, n bytes; the
+ * first 384 bytes suffice). No device work. Errors: HIZ_ERR_CORRUPT,
+ * HIZ_ERR_ARG. */
+hiz_status hiz_inspect(const void *h_stream, uint64_t n, hiz_info *out);
+
+/* Per-kernel timing of the calls made on this context while profiling is on
+ * (HIP events recorded on the caller's stream around each launch). */
+typedef struct {
+    char name[32];
+    uint64_t launches;
+    double total_ms;
+} hiz_kernel_stat;
+
+void hiz_set_profiling(hiz_ctx *ctx, int on);
+/* Copies up to `max` entries; returns the number of kernels seen. */
+int hiz_get_profile(hiz_ctx *ctx, hiz_kernel_stat *out, int max);
+void hiz_reset_profile(hiz_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

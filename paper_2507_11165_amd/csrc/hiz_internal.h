@@ -1,0 +1,200 @@
+// Internal declarations of the hiz GPU library: stream layout constants, the
+// per-field job descriptor the kernels read, the per-field device state the
+// kernels write, and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hiz {
+
+// ---- method constants (Sec. 5.1.1: 17^3 blocks, anchors every 16 points) ----
+constexpr int kAnchor = 16;
+constexpr int kSide = 17;
+constexpr int kLevels = 4;      // strides 8, 4, 2, 1
+constexpr int kMaxCodeLen = 32; // Huffman length cap
+constexpr int kCands = 14;      // tuner candidates: {LIN, CUB} x {MD, SEQ x 6 orders}
+
+// ---- stream layout (the paper leaves the container open; this one is ours) ----
+constexpr uint32_t kMagic = 0x315A4948u; // "HIZ1"
+constexpr uint16_t kVersion = 1;
+constexpr int kHdrBytes = 128;
+constexpr int kOffLen = 128;    // u8 code lengths [256]
+constexpr int kOffChunks = 384; // u32 words per chunk [n_chunks]
+// header field offsets
+constexpr int H_MAGIC = 0, H_VERSION = 4, H_MODE = 6, H_FLAGS = 7, H_DIMS = 8, H_EB = 32,
+              H_EPS = 40, H_MIN = 44, H_MAX = 48, H_ASTRIDE = 52, H_NLEV = 53, H_CFG = 56,
+              H_CHUNK = 68, H_NOUT = 72, H_PWORDS = 80, H_TOTAL = 88, H_NCHUNKS = 96,
+              H_NANCH = 104;
+constexpr uint8_t kFlagConst = 1, kFlagIdx64 = 2;
+
+__host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15u) & ~uint64_t(15); }
+__host__ __device__ inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// ---- status bits a kernel may raise for a field ----
+enum : uint32_t {
+    ST_CONST = 1u,     // constant field (REL mode, max == min)
+    ST_NONFINITE = 2u, // NaN/Inf in the input
+    ST_OVERFLOW = 4u,  // a write would pass the output capacity
+    ST_CORRUPT = 8u,   // decoder found an inconsistent stream
+};
+
+// Decoder lookup tables of one field, built once per decompression.
+constexpr int kLutBits = 11;
+struct DecTables {
+    uint16_t lut[1 << kLutBits]; // (len << 8) | symbol for codes up to kLutBits bits; 0 = slow path
+    uint32_t first[kMaxCodeLen + 2]; // first canonical code of each length
+    uint32_t count[kMaxCodeLen + 2]; // codes of each length
+    uint32_t index[kMaxCodeLen + 2]; // position of the first code of each length in `sorted`
+    uint8_t sorted[256];             // symbols by (length, symbol)
+    uint32_t maxlen;
+    uint32_t pad[3];
+};
+
+// Device-written state of one field. The first 64 bytes are what the host
+// reads back after a call.
+struct FieldState {
+    uint32_t flags;      // ST_* bits
+    uint32_t pad0;
+    uint64_t total_bytes;
+    uint64_t n_out;
+    uint64_t zeros_seen; // decoder: code-0 count
+    uint64_t payload_words;
+    uint32_t kmin, kmax; // ordered keys of the exact min / max
+    float vmin, vmax;
+    float eps, two_eb;
+    // ---- device-only ----
+    float inv;
+    uint32_t pad1;
+    double tune_scale;
+    uint8_t cfg[kLevels][3];
+    uint8_t pad2[4];
+    uint64_t off_oidx, off_oval, off_payload;
+    uint64_t hist[256];
+    uint64_t tune_err[kLevels][kCands];
+    uint32_t cb_code[256];
+    uint8_t cb_len[256];
+};
+constexpr int kResultBytes = 64;
+
+// Host-written, device-read description of one field of a (batched) call.
+struct Job {
+    const float *field;  // compress input
+    float *out;          // decompress output
+    uint8_t *stream;     // compress output / decompress input
+    uint64_t cap;        // stream capacity (compress) or size (decompress)
+    uint8_t *codes;      // N-byte code workspace
+    FieldState *st;
+    DecTables *dt;
+    uint64_t *lb_a;      // look-back status words (encoder: payload words; decoder: block words)
+    uint64_t *lb_b;      // look-back status words (encoder: outliers)
+    uint64_t dims[3];
+    uint64_t N;
+    uint32_t nb[3];      // blocks per axis = ceil(d / 16)
+    uint32_t ntz;        // tiles along z = ceil(nb[2] / tile_z)
+    uint64_t n_anchors;
+    uint64_t n_chunks;
+    uint64_t off_anchors;
+    uint32_t chunk, log2_chunk;
+    int32_t mode;
+    int32_t tune;
+    double eb;
+    uint8_t cfg_forced[kLevels][3];
+    uint8_t idx_bytes;
+    uint8_t pad[3];
+    // prefix offsets of this field's work units in each batched work list
+    uint64_t mm_begin, tune_begin, tile_begin, chunk_begin, dblk_begin, out_begin;
+    uint64_t n_mm, n_tune, n_tiles, n_dblk;
+    uint32_t n_full[3];  // full 17^3 blocks per axis (tuner sample)
+    uint32_t n_samples;  // tuner sample size
+    // decompression: section layout and bound parsed from the header
+    uint64_t off_oidx, off_oval, off_payload, n_out, payload_words;
+    float eps;
+    uint32_t pad2;
+};
+
+// Work list shared by a launch: njobs fields and their concatenated units.
+struct JobList {
+    const Job *jobs;
+    int njobs;
+    uint64_t total; // total units of the launch's work kind
+};
+
+// Counters reset at the start of every call.
+struct Counters {
+    uint32_t enc_next;
+    uint32_t dec_next;
+    uint32_t pad[14];
+};
+
+// ---- kernel launchers (each defined next to its kernel) ----
+enum WorkKind { WK_MM, WK_TUNE, WK_TILE, WK_CHUNK, WK_DBLK, WK_OUT };
+
+void launch_init_compress(const Job *d_jobs, int njobs, uint64_t max_chunks, Counters *cnt,
+                          hipStream_t s);
+void launch_minmax(const Job *d_jobs, int njobs, uint64_t total, int grid, hipStream_t s);
+void launch_eps(const Job *d_jobs, int njobs, hipStream_t s);
+void launch_tune(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s);
+void launch_tune_pick(const Job *d_jobs, int njobs, hipStream_t s);
+void launch_predict(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
+                    hipStream_t s);
+int predict_blocks_per_cu(int tile_z);
+void launch_codebook(const Job *d_jobs, int njobs, hipStream_t s);
+void launch_encode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, int grid,
+                   hipStream_t s);
+int encode_blocks_per_cu();
+
+void launch_fill(float *out, uint64_t n, float v, hipStream_t s);
+void launch_init_decompress(const Job *d_jobs, int njobs, uint64_t max_blocks, Counters *cnt,
+                            hipStream_t s);
+void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s);
+void launch_decode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, hipStream_t s);
+void launch_scatter(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s);
+void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
+                        hipStream_t s);
+int reconstruct_blocks_per_cu(int tile_z);
+
+// ---- device helpers shared by the kernels ----
+#ifdef __HIPCC__
+// Unit u of a launch's work list -> job index (binary search over prefixes).
+template <WorkKind K>
+__device__ inline uint64_t job_begin(const Job &j)
+{
+    switch (K) {
+    case WK_MM: return j.mm_begin;
+    case WK_TUNE: return j.tune_begin;
+    case WK_TILE: return j.tile_begin;
+    case WK_CHUNK: return j.chunk_begin;
+    case WK_DBLK: return j.dblk_begin;
+    default: return j.out_begin;
+    }
+}
+
+template <WorkKind K>
+__device__ inline int find_job(const Job *jobs, int njobs, uint64_t u)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (job_begin<K>(jobs[mid]) <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Ordered 32-bit key of a float: unsigned order == total order (-0 < +0).
+__device__ inline uint32_t fkey(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline float fkey_inv(uint32_t k)
+{
+    uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(b);
+}
+#endif
+
+} // namespace hiz

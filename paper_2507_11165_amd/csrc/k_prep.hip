@@ -1,0 +1,427 @@
+// Preparation kernels of compression: state reset, exact min/max of the field,
+// the absolute error bound (Sec. 3.1 Eq. "general", Sec. 6.1.4) and the
+// sampled-block tuner (Sec. 5.1.3).
+#include "hiz_internal.h"
+
+namespace hiz {
+
+// ---------------------------------------------------------------------------
+// Reset of per-field state and look-back flags (a fill kernel rather than
+// hipMemsetAsync so that the sequence can be captured in a HIP graph).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init_compress(const Job *__restrict__ jobs, int njobs,
+                                                       Counters *cnt)
+{
+    const Job &J = jobs[blockIdx.y];
+    FieldState *st = J.st;
+    const uint32_t t = threadIdx.x;
+    if (blockIdx.x == 0) {
+        st->hist[t] = 0;
+        if (t < kLevels * kCands)
+            (&st->tune_err[0][0])[t] = 0;
+        if (t == 0) {
+            st->kmin = 0xffffffffu;
+            st->kmax = 0u;
+            st->flags = 0u;
+            st->n_out = 0;
+            st->payload_words = 0;
+            st->total_bytes = 0;
+            st->zeros_seen = 0;
+        }
+        if (blockIdx.y == 0 && t < sizeof(Counters) / 4)
+            reinterpret_cast<uint32_t *>(cnt)[t] = 0u;
+    }
+    for (uint64_t i = blockIdx.x * 256ull + t; i < J.n_chunks; i += 256ull * gridDim.x) {
+        J.lb_a[i] = 0;
+        J.lb_b[i] = 0;
+    }
+}
+
+void launch_init_compress(const Job *d_jobs, int njobs, uint64_t max_chunks, Counters *cnt,
+                          hipStream_t s)
+{
+    uint64_t gx = cdiv(max_chunks, 256);
+    if (gx < 1)
+        gx = 1;
+    if (gx > 1024)
+        gx = 1024;
+    hipLaunchKernelGGL(k_init_compress, dim3((uint32_t)gx, njobs), dim3(256), 0, s, d_jobs, njobs,
+                       cnt);
+}
+
+// ---------------------------------------------------------------------------
+// Exact min/max (REL mode): ordered 32-bit keys reduced with atomics, so the
+// result does not depend on the order of reduction; NaN/Inf raise a flag.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kMmUnit = 16384; // elements per work unit
+
+__device__ inline uint32_t wave_min_u32(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_minmax(const Job *__restrict__ jobs, int njobs,
+                                                uint64_t total)
+{
+    const uint32_t t = threadIdx.x;
+    for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
+        const Job &J = jobs[find_job<WK_MM>(jobs, njobs, u)];
+        const uint64_t lo = (u - J.mm_begin) * kMmUnit;
+        const uint64_t hi = min(lo + kMmUnit, J.N);
+        const float *f = J.field;
+        uint32_t kmn = 0xffffffffu, kmx = 0u;
+        bool bad = false;
+        const bool vec = ((reinterpret_cast<uintptr_t>(f) & 15u) == 0) && (hi - lo == kMmUnit);
+        if (vec) {
+            const float4 *f4 = reinterpret_cast<const float4 *>(f + lo);
+#pragma unroll 4
+            for (int k = 0; k < (int)(kMmUnit / 4 / 256); k++) {
+                const float4 q = f4[k * 256 + t];
+                float e[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    bad |= !isfinite(e[i]);
+                    uint32_t key = fkey(e[i]);
+                    kmn = min(kmn, key);
+                    kmx = max(kmx, key);
+                }
+            }
+        } else {
+            for (uint64_t i = lo + t; i < hi; i += 256) {
+                float e = f[i];
+                bad |= !isfinite(e);
+                uint32_t key = fkey(e);
+                kmn = min(kmn, key);
+                kmx = max(kmx, key);
+            }
+        }
+        kmn = wave_min_u32(kmn);
+        kmx = wave_max_u32(kmx);
+        int anybad = __any(bad);
+        if ((t & 63) == 0) {
+            atomicMin(&J.st->kmin, kmn);
+            atomicMax(&J.st->kmax, kmx);
+            if (anybad)
+                atomicOr(&J.st->flags, (uint32_t)ST_NONFINITE);
+        }
+    }
+}
+
+void launch_minmax(const Job *d_jobs, int njobs, uint64_t total, int grid, hipStream_t s)
+{
+    if (total == 0)
+        return;
+    uint64_t g = total < (uint64_t)grid ? total : (uint64_t)grid;
+    hipLaunchKernelGGL(k_minmax, dim3((uint32_t)g), dim3(256), 0, s, d_jobs, njobs, total);
+}
+
+// ---------------------------------------------------------------------------
+// Error bound: eps = eb (ABS) or eb * (max - min) (REL), formed in FP64 and
+// rounded down to FP32 so that it never exceeds the requested bound.
+// ---------------------------------------------------------------------------
+__global__ void k_eps(const Job *__restrict__ jobs, int njobs)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs)
+        return;
+    const Job &J = jobs[j];
+    FieldState *st = J.st;
+    double e = J.eb;
+    if (J.mode == 1) {
+        if (st->flags & ST_NONFINITE)
+            return;
+        float vmin = fkey_inv(st->kmin), vmax = fkey_inv(st->kmax);
+        st->vmin = vmin;
+        st->vmax = vmax;
+        double range = (double)vmax - (double)vmin;
+        if (range == 0.0) {
+            st->flags |= ST_CONST;
+            return;
+        }
+        e = J.eb * range;
+    }
+    float f = (float)e;
+    if ((double)f > e)
+        f = nextafterf(f, 0.0f);
+    st->eps = f;
+    st->two_eb = f * 2.0f;
+    st->inv = 1.0f / st->two_eb;
+    st->tune_scale = f > 0.0f ? 65536.0 / (2.0 * (double)f) : 65536.0;
+}
+
+void launch_eps(const Job *d_jobs, int njobs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_eps, dim3((njobs + 63) / 64), dim3(64), 0, s, d_jobs, njobs);
+}
+
+// ---------------------------------------------------------------------------
+// Tuner (Sec. 5.1.3). Full 17^3 blocks with 0.2 % of the volume are sampled at
+// even spacing. Every level is tested with the 14 candidates {LIN, CUB} x
+// {MD, SEQ over the 6 dimension orders}, predicting from ORIGINAL values; the
+// candidate with the smallest aggregated |x - p| wins per level (ties: lower
+// index). Each |x - p| is counted in units of 2*eps/65536, rounded and capped
+// at 2^36, and summed as a 64-bit integer, so the totals are exact and do not
+// depend on the reduction order.
+//
+// Work balance follows the paper's idea of giving the expensive fine levels
+// more thread blocks: per sample, one block tests strides 8 and 4, two
+// blocks share stride 2 and six share stride 1. Unlike the paper, each block
+// tests all 14 candidates on its share of targets, because the candidates
+// reuse the same per-axis stencils.
+// ---------------------------------------------------------------------------
+constexpr int kTuneParts = 9;
+
+__constant__ int8_t c_perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+// 1-D spline stencil (Sec. 5.1.2): Lagrange weights at the midpoint from the
+// samples at -3s, -s, +s, +3s; lower orders where samples are missing.
+__device__ __forceinline__ float stencil_1d(float a, float b, float c, float d, bool pa, bool pc,
+                                            bool pd, bool cub, int &rank)
+{
+    if (cub && pa && pc && pd) {
+        rank = 4;
+        return ((b + c) * 9.0f - (a + d)) * 0.0625f;
+    }
+    if (cub && pc && pd) {
+        rank = 3;
+        return ((b * 3.0f + c * 6.0f) - d) * 0.125f;
+    }
+    if (cub && pa && pc) {
+        rank = 3;
+        return ((b * 6.0f + c * 3.0f) - a) * 0.125f;
+    }
+    if (pc) {
+        rank = 2;
+        return (b + c) * 0.5f;
+    }
+    if (pa) {
+        rank = 1;
+        return b * 1.5f - a * 0.5f;
+    }
+    rank = 0;
+    return b;
+}
+
+// Mean of the predictions of maximal rank, combined in x, y, z order.
+__device__ __forceinline__ float md_combine(const float p[3], const int r[3], int mask)
+{
+    int best = -1;
+    for (int k = 0; k < 3; k++)
+        if ((mask >> k) & 1)
+            best = max(best, r[k]);
+    bool u0 = (mask & 1) && r[0] == best, u1 = (mask & 2) && r[1] == best,
+         u2 = (mask & 4) && r[2] == best;
+    int m = (int)u0 + (int)u1 + (int)u2;
+    float first = u0 ? p[0] : (u1 ? p[1] : p[2]);
+    float second = u0 ? (u1 ? p[1] : p[2]) : p[2];
+    if (m == 1)
+        return first;
+    if (m == 2)
+        return (first + second) * 0.5f;
+    return ((p[0] + p[1]) + p[2]) / 3.0f;
+}
+
+__device__ __forceinline__ uint64_t tune_term(float x, float p, double scale)
+{
+    float e = fabsf(x - p);
+    double w = (double)e * scale;
+    const double cap = 68719476736.0; // 2^36
+    return (w < cap) ? (uint64_t)(w + 0.5) : (uint64_t)cap;
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+        lo = (uint32_t)__shfl_xor((int)lo, o, 64);
+        hi = (uint32_t)__shfl_xor((int)hi, o, 64);
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+// Accumulate the 14 candidate error sums of the targets [g0, g1) of the
+// stride-s grid of a block held in LDS (side 17).
+__device__ void tune_level(const float *__restrict__ blk, int s, int g0, int g1, double scale,
+                           uint64_t acc[kCands])
+{
+    const int G = 16 / s + 1;
+    for (int g = g0 + (int)threadIdx.x; g < g1; g += blockDim.x) {
+        int iz = g % G, r = g / G, iy = r % G, ix = r / G;
+        int mask = (ix & 1) | ((iy & 1) << 1) | ((iz & 1) << 2);
+        if (mask == 0)
+            continue;
+        int t[3] = {ix * s, iy * s, iz * s};
+        const int st[3] = {kSide * kSide, kSide, 1};
+        int li = (t[0] * kSide + t[1]) * kSide + t[2];
+        float pl[3] = {0, 0, 0}, pc3[3] = {0, 0, 0};
+        int rl[3] = {-1, -1, -1}, rc[3] = {-1, -1, -1};
+        for (int k = 0; k < 3; k++) {
+            if (!((mask >> k) & 1))
+                continue;
+            int tk = t[k];
+            bool pa = tk - 3 * s >= 0, pcp = tk + s <= kSide - 1, pd = tk + 3 * s <= kSide - 1;
+            float b = blk[li - s * st[k]];
+            float a = pa ? blk[li - 3 * s * st[k]] : 0.0f;
+            float c = pcp ? blk[li + s * st[k]] : 0.0f;
+            float d = pd ? blk[li + 3 * s * st[k]] : 0.0f;
+            pl[k] = stencil_1d(a, b, c, d, pa, pcp, pd, false, rl[k]);
+            pc3[k] = stencil_1d(a, b, c, d, pa, pcp, pd, true, rc[k]);
+        }
+        float x = blk[li];
+        acc[0] += tune_term(x, md_combine(pl, rl, mask), scale);
+        acc[7] += tune_term(x, md_combine(pc3, rc, mask), scale);
+        for (int perm = 0; perm < 6; perm++) {
+            int axis = -1;
+            for (int j = 0; j < 3; j++)
+                if ((mask >> c_perm[perm][j]) & 1)
+                    axis = c_perm[perm][j];
+            float vl = axis == 0 ? pl[0] : (axis == 1 ? pl[1] : pl[2]);
+            float vc = axis == 0 ? pc3[0] : (axis == 1 ? pc3[1] : pc3[2]);
+            acc[1 + perm] += tune_term(x, vl, scale);
+            acc[8 + perm] += tune_term(x, vc, scale);
+        }
+    }
+}
+
+__device__ void tune_flush(FieldState *st, int level, uint64_t acc[kCands], uint64_t *red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = 0; c < kCands; c++) {
+        uint64_t v = wave_sum_u64(acc[c]);
+        if (lane == 0)
+            red[wave * kCands + c] = v;
+        acc[c] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < kCands) {
+        uint64_t v = 0;
+        for (int w = 0; w < nw; w++)
+            v += red[w * kCands + threadIdx.x];
+        if (v)
+            atomicAdd((unsigned long long *)&st->tune_err[level][threadIdx.x],
+                      (unsigned long long)v);
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_tune(const Job *__restrict__ jobs, int njobs,
+                                              uint64_t total)
+{
+    __shared__ float blk[kSide * kSide * kSide];
+    __shared__ uint64_t red[4 * kCands];
+    const uint64_t u = blockIdx.x;
+    if (u >= total)
+        return;
+    const Job &J = jobs[find_job<WK_TUNE>(jobs, njobs, u)];
+    FieldState *st = J.st;
+    if (st->flags & (ST_CONST | ST_NONFINITE))
+        return;
+    const uint64_t lu = u - J.tune_begin;
+    const uint64_t j = lu / kTuneParts;
+    const int part = (int)(lu % kTuneParts);
+    const uint64_t n_full = (uint64_t)J.n_full[0] * J.n_full[1] * J.n_full[2];
+    const uint64_t idx = ((2 * j + 1) * n_full) / (2 * (uint64_t)J.n_samples);
+    const uint64_t bc = idx % J.n_full[2], bb = (idx / J.n_full[2]) % J.n_full[1],
+                   ba = idx / ((uint64_t)J.n_full[1] * J.n_full[2]);
+    const uint64_t dy = J.dims[1], dz = J.dims[2];
+    for (int i = threadIdx.x; i < kSide * kSide * kSide; i += blockDim.x) {
+        int z = i % kSide, r = i / kSide, y = r % kSide, x = r / kSide;
+        blk[i] = J.field[((ba * kAnchor + x) * dy + (bb * kAnchor + y)) * dz + bc * kAnchor + z];
+    }
+    __syncthreads();
+    const double scale = st->tune_scale;
+    uint64_t acc[kCands];
+    for (int c = 0; c < kCands; c++)
+        acc[c] = 0;
+    if (part == 0) {
+        tune_level(blk, 8, 0, 27, scale, acc);
+        tune_flush(st, 0, acc, red);
+        tune_level(blk, 4, 0, 125, scale, acc);
+        tune_flush(st, 1, acc, red);
+    } else if (part <= 2) {
+        const int G3 = 9 * 9 * 9, h = part - 1;
+        tune_level(blk, 2, h * G3 / 2, (h + 1) * G3 / 2, scale, acc);
+        tune_flush(st, 2, acc, red);
+    } else {
+        const int G3 = kSide * kSide * kSide, h = part - 3;
+        tune_level(blk, 1, h * G3 / 6, (h + 1) * G3 / 6, scale, acc);
+        tune_flush(st, 3, acc, red);
+    }
+}
+
+void launch_tune(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s)
+{
+    if (total == 0)
+        return;
+    hipLaunchKernelGGL(k_tune, dim3((uint32_t)total), dim3(256), 0, s, d_jobs, njobs, total);
+}
+
+// Per-level argmin (ties to the lower candidate), or the forced/default
+// configuration when the tuner is off or no full block exists.
+__global__ void k_tune_pick(const Job *__restrict__ jobs, int njobs)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs)
+        return;
+    const Job &J = jobs[j];
+    FieldState *st = J.st;
+    for (int l = 0; l < kLevels; l++) {
+        uint8_t sp, sc, pm;
+        if (J.tune && J.n_samples > 0) {
+            int best = 0;
+            for (int c = 1; c < kCands; c++)
+                if (st->tune_err[l][c] < st->tune_err[l][best])
+                    best = c;
+            int r = best % 7;
+            sp = (uint8_t)(best / 7);
+            sc = (uint8_t)(r == 0 ? 0 : 1);
+            pm = (uint8_t)(r == 0 ? 0 : r - 1);
+        } else if (J.tune) {
+            sp = 1;
+            sc = 0;
+            pm = 0;
+        } else {
+            sp = J.cfg_forced[l][0];
+            sc = J.cfg_forced[l][1];
+            pm = J.cfg_forced[l][2];
+        }
+        st->cfg[l][0] = sp;
+        st->cfg[l][1] = sc;
+        st->cfg[l][2] = pm;
+    }
+}
+
+void launch_tune_pick(const Job *d_jobs, int njobs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tune_pick, dim3((njobs + 63) / 64), dim3(64), 0, s, d_jobs, njobs);
+}
+
+// ---------------------------------------------------------------------------
+// Constant-field decompression: every element gets the stored value.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill(float *out, uint64_t n, float v)
+{
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += 256ull * gridDim.x)
+        out[i] = v;
+}
+
+void launch_fill(float *out, uint64_t n, float v, hipStream_t s)
+{
+    uint64_t g = cdiv(n, 256);
+    if (g > 4096)
+        g = 4096;
+    if (g < 1)
+        g = 1;
+    hipLaunchKernelGGL(k_fill, dim3((uint32_t)g), dim3(256), 0, s, out, n, v);
+}
+
+} // namespace hiz
