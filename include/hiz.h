@@ -121,7 +121,8 @@ hiz_status hiz_decompress(hiz_ctx *ctx, const void *d_in, uint64_t in_size,
                           hiz_stream_t stream);
 
 /* Parse the header of a stream held in HOST memory (h_stream, n bytes; the
- * first 384 bytes suffice). No device work. Errors: HIZ_ERR_CORRUPT,
+ * first 384 bytes suffice, a prefix of the stream is enough). Checks the
+ * header's internal consistency only. No device work. Errors: HIZ_ERR_CORRUPT,
  * HIZ_ERR_ARG. */
 hiz_status hiz_inspect(const void *h_stream, uint64_t n, hiz_info *out);
 

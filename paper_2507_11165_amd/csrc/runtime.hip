@@ -580,7 +580,9 @@ hiz_status hiz_inspect(const void *h_stream, uint64_t n, hiz_info *out)
     if (!h_stream || !out)
         return HIZ_ERR_ARG;
     Parsed P;
-    hiz_status rc = parse_header(nullptr, static_cast<const uint8_t *>(h_stream), n, n, &P);
+    // only the header is checked: the bytes given may be a prefix of the stream
+    hiz_status rc =
+        parse_header(nullptr, static_cast<const uint8_t *>(h_stream), n, ~uint64_t(0), &P);
     if (rc)
         return rc;
     *out = P.info;
