@@ -1,0 +1,213 @@
+"""Benchmark: compress + decompress throughput of one FP32 3-D field on one GPU.
+
+Workload: 512^3 Gaussian random field with the Kolmogorov spectrum k^-11/3 plus
+1 % white noise (fieldgen.field_turb), value-range relative bound 1e-3, tuner
+on; input and output resident in HBM. A step is one compression followed by
+one decompression of the field. `value` = (4N bytes in + 4N bytes out) /
+(compress time + decompress time), i.e. 8N / (t_c + t_d).
+
+The roofline entry covers the kernel with the largest share of the timed
+region: its algorithmic bytes per launch divided by its mean launch time,
+measured with HIP events on the launch stream inside the timed region.
+The CPU baseline is the oracle (single-threaded C) on a bounded slab of the
+same field.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eb 1e-3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(name, N, info, n_anchors):
+    """Bytes the method must move per launch of each kernel."""
+    n_out = info["n_outliers"]
+    pw = info["payload_words"]
+    nch = info["n_chunks"]
+    ib = 4 if N < 2 ** 32 else 8
+    table = {
+        "minmax": 4 * N,
+        "predict_quant": 4 * N + N + 4 * n_anchors,
+        "encode": N + 4 * pw + 4 * nch + (ib + 4) * n_out + 4 * n_out,
+        "decode": 4 * pw + 4 * nch + N,
+        "scatter": (ib + 4) * n_out + 4 * n_out,
+        "reconstruct": N + 4 * N + 4 * n_anchors + 4 * n_out,
+    }
+    return table.get(name)
+
+
+def cpu_baseline(x, eb, planes):
+    """Oracle compress + decompress of the first `planes` x-planes (one core)."""
+    import oracle as O
+    sample = np.ascontiguousarray(x[:planes])
+    t0 = time.perf_counter()
+    r = O.compress(sample, O.REL, eb, tune=True, chunk=1024, debug=False)
+    t1 = time.perf_counter()
+    O.decompress(r.stream)
+    t2 = time.perf_counter()
+    gbs = 8.0 * sample.size / (t2 - t0) / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {planes} x-planes of the same field ({sample.shape}, "
+                      f"{sample.nbytes / 1e6:.0f} MB), compress {t1 - t0:.2f} s + "
+                      f"decompress {t2 - t1:.2f} s, single-threaded C"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--eb", type=float, default=1e-3)
+    ap.add_argument("--tile-z", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--cpu-planes", type=int, default=192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the compressor's data-parallel path runs on a "
+              "single device here (multi-GPU sharding is described in DESIGN.md, not run)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import fieldgen
+    from paper_2507_11165_amd import hiz
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    log("generating 512^3 field (k^-11/3 + 1% noise)")
+    t = time.time()
+    x = fieldgen.field_turb()
+    log(f"  generated in {time.time() - t:.1f}s")
+    N = x.size
+    shape = x.shape
+    xd = torch.from_numpy(x).to(dev)
+    ctx = hiz.Context(0)
+    params = hiz.make_params(tune=True, chunk=args.chunk, tile_z=args.tile_z)
+    cap = 5 * N + (1 << 20)
+    zbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    ybuf = torch.empty(shape, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    sh = hiz.C.c_void_p(stream.cuda_stream)
+
+    def step():
+        size = ctx.compress_ptr(xd.data_ptr(), shape, "rel", args.eb, zbuf.data_ptr(), cap,
+                                params, sh)
+        ctx.decompress_ptr(zbuf.data_ptr(), size, ybuf.data_ptr(), N, sh)
+        return size
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        size = step()
+    torch.cuda.synchronize()
+
+    # timed region: whole steps, then per-kernel HIP-event times of the same region
+    ctx.reset_profile()
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        size = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    prof = ctx.profile()
+    elapsed = t1 - t0
+    log(f"timed {args.steps} steps in {elapsed:.3f}s")
+
+    # separate compress / decompress timing (not the headline; for the record)
+    torch.cuda.synchronize()
+    tc0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.compress_ptr(xd.data_ptr(), shape, "rel", args.eb, zbuf.data_ptr(), cap, params, sh)
+    torch.cuda.synchronize()
+    tc1 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.decompress_ptr(zbuf.data_ptr(), size, ybuf.data_ptr(), N, sh)
+    torch.cuda.synchronize()
+    tc2 = time.perf_counter()
+    t_c = (tc1 - tc0) / args.steps
+    t_d = (tc2 - tc1) / args.steps
+
+    zh = zbuf[:size].cpu().numpy()
+    info = hiz.inspect(zh[:512].tobytes())
+    y = ybuf.cpu().numpy()
+    err = np.abs(x.astype(np.float64) - y.astype(np.float64))
+    maxerr = float(err.max())
+    rng = float(x.max()) - float(x.min())
+    mse = float(np.mean(err ** 2))
+    psnr = 20 * np.log10(rng) - 10 * np.log10(mse) if mse > 0 else float("inf")
+    if maxerr > info["eps"]:
+        raise SystemExit(f"error bound violated: {maxerr} > {info['eps']}")
+
+    n_anchors = int(np.prod([-(-d // 16) for d in shape]))
+    kernels = {}
+    dom, dom_ms = None, -1.0
+    for name, (launches, ms) in prof.items():
+        kernels[name] = {"launches": launches, "mean_ms": round(ms / max(launches, 1), 5)}
+        if ms > dom_ms:
+            dom, dom_ms = name, ms
+    launches, ms = prof[dom]
+    mean_s = ms / launches / 1e3
+    algo = algorithmic_bytes(dom, N, info, n_anchors)
+    achieved = algo / mean_s / 1e9 if algo else None
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1) if achieved else None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                "traffic": None, "algorithmic_bytes_per_launch": algo,
+                "mean_launch_ms": round(mean_s * 1e3, 5)}
+    value = 8.0 * N * args.steps / elapsed / 1e9
+    res = {
+        "metric": "compress+decompress GB/s & % HBM peak at eb=1e-3; ratio; batched vs plain",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "single 512x512x512 FP32 field, GRF k^-11/3 + 1% white noise, rel eb 1e-3",
+            "dims": list(shape), "eb_mode": "rel", "eb": args.eb,
+            "chunk": info["chunk"], "tile_z": args.tile_z or 2,
+            "level_cfg": info["level_cfg"],
+        },
+        "compress_GBps": round(4.0 * N / t_c / 1e9, 2),
+        "decompress_GBps": round(4.0 * N / t_d / 1e9, 2),
+        "effective_hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        "ratio": round(4.0 * N / size, 4),
+        "bits_per_value": round(32.0 * size / (4.0 * N), 4),
+        "psnr_db": round(float(psnr), 3),
+        "max_err_over_eps": round(maxerr / info["eps"], 6),
+        "outlier_frac": round(info["n_outliers"] / N, 6),
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on {args.cpu_planes} planes")
+        res["cpu_baseline"] = cpu_baseline(x, args.eb, args.cpu_planes)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
