@@ -86,8 +86,11 @@ struct Job {
     uint8_t *codes;      // N-byte code workspace
     FieldState *st;
     DecTables *dt;
-    uint64_t *lb_a;      // look-back status words (encoder: payload words; decoder: block words)
-    uint64_t *lb_b;      // look-back status words (encoder: outliers)
+    uint64_t *lb_a;      // look-back status words (encoder groups: payload words; decoder blocks)
+    uint64_t *lb_b;      // look-back status words (encoder groups: outliers)
+    uint64_t *woff;      // encoder: payload word offset of each chunk
+    uint64_t *zoff;      // encoder: first outlier slot of each chunk
+    uint2 *mm_part;      // per-unit (min, max) key partials: minmax units (REL) or tiles (ABS)
     uint64_t dims[3];
     uint64_t N;
     uint32_t nb[3];      // blocks per axis = ceil(d / 16)
@@ -103,8 +106,8 @@ struct Job {
     uint8_t idx_bytes;
     uint8_t pad[3];
     // prefix offsets of this field's work units in each batched work list
-    uint64_t mm_begin, tune_begin, tile_begin, chunk_begin, dblk_begin, out_begin;
-    uint64_t n_mm, n_tune, n_tiles, n_dblk;
+    uint64_t mm_begin, tune_begin, tile_begin, chunk_begin, group_begin, dblk_begin, out_begin;
+    uint64_t n_mm, n_tune, n_tiles, n_groups, n_dblk;
     uint32_t n_full[3];  // full 17^3 blocks per axis (tuner sample)
     uint32_t n_samples;  // tuner sample size
     // decompression: section layout and bound parsed from the header
@@ -128,7 +131,8 @@ struct Counters {
 };
 
 // ---- kernel launchers (each defined next to its kernel) ----
-enum WorkKind { WK_MM, WK_TUNE, WK_TILE, WK_CHUNK, WK_DBLK, WK_OUT };
+enum WorkKind { WK_MM, WK_TUNE, WK_TILE, WK_CHUNK, WK_GROUP, WK_DBLK, WK_OUT };
+constexpr int kEncGroupChunks = 64; // chunks per workgroup of the encoder's sizing pass
 
 void launch_init_compress(const Job *d_jobs, int njobs, uint64_t max_chunks, Counters *cnt,
                           hipStream_t s);
@@ -140,8 +144,8 @@ void launch_predict(const Job *d_jobs, int njobs, uint64_t total, int tile_z, in
                     hipStream_t s);
 int predict_blocks_per_cu(int tile_z);
 void launch_codebook(const Job *d_jobs, int njobs, hipStream_t s);
-void launch_encode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, int grid,
-                   hipStream_t s);
+void launch_encode(const Job *d_jobs, int njobs, uint64_t total_chunks, uint64_t total_groups,
+                   Counters *cnt, int grid, hipStream_t s);
 int encode_blocks_per_cu();
 
 void launch_fill(float *out, uint64_t n, float v, hipStream_t s);
@@ -165,6 +169,7 @@ __device__ inline uint64_t job_begin(const Job &j)
     case WK_TUNE: return j.tune_begin;
     case WK_TILE: return j.tile_begin;
     case WK_CHUNK: return j.chunk_begin;
+    case WK_GROUP: return j.group_begin;
     case WK_DBLK: return j.dblk_begin;
     default: return j.out_begin;
     }
@@ -182,6 +187,43 @@ __device__ inline int find_job(const Job *jobs, int njobs, uint64_t u)
             hi = mid - 1;
     }
     return lo;
+}
+
+// Min/max of ordered keys over a workgroup of 256 threads; result in lane 0
+// of wave 0 (other threads get partial values). `red` is 8 words of LDS.
+__device__ inline void block_minmax(uint32_t &kmn, uint32_t &kmx, uint32_t *red)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        kmn = min(kmn, (uint32_t)__shfl_xor((int)kmn, o, 64));
+        kmx = max(kmx, (uint32_t)__shfl_xor((int)kmx, o, 64));
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[2 * wv] = kmn;
+        red[2 * wv + 1] = kmx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) {
+            kmn = min(kmn, red[2 * w]);
+            kmx = max(kmx, red[2 * w + 1]);
+        }
+    }
+    __syncthreads();
+}
+
+// Reduce n (min, max) key partials with the whole workgroup (result in thread 0).
+__device__ inline void reduce_partials(const uint2 *p, uint64_t n, uint32_t &kmn, uint32_t &kmx,
+                                       uint32_t *red)
+{
+    kmn = 0xffffffffu;
+    kmx = 0u;
+    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint2 v = p[i];
+        kmn = min(kmn, v.x);
+        kmx = max(kmx, v.y);
+    }
+    block_minmax(kmn, kmx, red);
 }
 
 // Ordered 32-bit key of a float: unsigned order == total order (-0 < +0).

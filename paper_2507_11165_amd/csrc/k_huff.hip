@@ -25,35 +25,59 @@ __device__ inline void lb_store(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ uint64_t lookback(uint64_t *arr, uint64_t idx, uint64_t agg)
-{
-    if (idx == 0) {
-        lb_store(&arr[0], LB_INC | agg);
-        return 0;
-    }
-    lb_store(&arr[idx], LB_AGG | agg);
-    uint64_t excl = 0, j = idx - 1;
-    for (;;) {
-        const uint64_t w = lb_load(&arr[j]);
-        const uint64_t f = w >> 62;
-        if (f == 0) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        excl += w & LB_MASK;
-        if (f == 2 || j == 0)
-            break;
-        j--;
-    }
-    lb_store(&arr[idx], LB_INC | (excl + agg));
-    return excl;
-}
-
 __device__ inline uint64_t shfl64(uint64_t v, int src)
 {
     uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
     uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
     return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t wave_sum64(uint64_t v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int o = 32; o > 0; o >>= 1)
+        v += shfl64(v, lane ^ o);
+    return v;
+}
+
+// Exclusive prefix of unit `idx` (called by all 64 lanes of one wave). The
+// wave reads the statuses of 64 predecessors per round trip; it stops at the
+// nearest inclusive prefix once every unit between is at least published.
+__device__ uint64_t lookback(uint64_t *arr, uint64_t idx, uint64_t agg)
+{
+    const int lane = threadIdx.x & 63;
+    if (idx == 0) {
+        if (lane == 0)
+            lb_store(&arr[0], LB_INC | agg);
+        return 0;
+    }
+    if (lane == 0)
+        lb_store(&arr[idx], LB_AGG | agg);
+    uint64_t excl = 0;
+    int64_t end = (int64_t)idx;
+    for (;;) {
+        const int64_t j = end - 1 - lane;
+        const uint64_t w = j >= 0 ? lb_load(&arr[j]) : LB_INC; // before unit 0: inclusive 0
+        const uint64_t f = w >> 62;
+        const uint64_t inc = __ballot(f == 2);
+        const uint64_t empty = __ballot(f == 0);
+        if (inc) {
+            const int p = __ffsll((unsigned long long)inc) - 1;
+            const uint64_t need = (p == 63) ? ~0ull : ((2ull << p) - 1);
+            if ((empty & need) == 0) {
+                excl += wave_sum64(lane <= p ? (w & LB_MASK) : 0);
+                break;
+            }
+        } else if (empty == 0) {
+            excl += wave_sum64(w & LB_MASK);
+            end -= 64;
+            continue;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0)
+        lb_store(&arr[idx], LB_INC | (excl + agg));
+    return excl;
 }
 
 __device__ inline uint32_t wave_incl_scan(uint32_t v)
@@ -134,7 +158,6 @@ __global__ __launch_bounds__(256) void k_codebook(const Job *__restrict__ jobs, 
     __shared__ uint64_t cnt[256];
     __shared__ uint64_t w[512];
     __shared__ int16_t par[512];
-    __shared__ uint8_t dep[512];
     __shared__ uint8_t leafsym[256];
     __shared__ uint8_t len[256];
     __shared__ uint64_t blc[kMaxCodeLen + 2];
@@ -148,7 +171,24 @@ __global__ __launch_bounds__(256) void k_codebook(const Job *__restrict__ jobs, 
         return;
     uint8_t *out = J.stream;
     const uint64_t cap = J.cap;
-    const float vmin = fkey_inv(st->kmin), vmax = fkey_inv(st->kmax);
+    __shared__ uint32_t red[8];
+    __shared__ uint32_t s_kmin, s_kmax;
+    if (J.mode == 0) {
+        // ABS mode: exact min/max from the prediction kernel's per-tile partials
+        uint32_t kmn, kmx;
+        reduce_partials(J.mm_part, J.n_tiles, kmn, kmx, red);
+        if (t == 0) {
+            s_kmin = kmn;
+            s_kmax = kmx;
+            st->kmin = kmn;
+            st->kmax = kmx;
+        }
+    } else if (t == 0) {
+        s_kmin = st->kmin;
+        s_kmax = st->kmax;
+    }
+    __syncthreads();
+    const float vmin = fkey_inv(s_kmin), vmax = fkey_inv(s_kmax);
     if (flags & ST_CONST) {
         if (t < kLevels * 3)
             s_cfg[t / 3][t % 3] = (t % 3 == 0) ? 1 : 0;
@@ -190,37 +230,58 @@ __global__ __launch_bounds__(256) void k_codebook(const Job *__restrict__ jobs, 
         len[t] = 0;
         __syncthreads();
         if (t == 0) {
-            int maxlen = 0;
             if (n == 1) {
                 len[leafsym[0]] = 1;
-                maxlen = 1;
             } else if (n > 1) {
+                // nodes 0..n-1: sorted leaves; n..2n-2: merged nodes in creation order
+                const uint64_t INF = ~0ull;
                 int lq = 0, iq = n, next = n;
+                uint64_t wl = w[0], wi = INF;
                 for (int step = 0; step < n - 1; step++) {
                     int p0, p1;
-                    if (lq < n && (iq >= next || w[lq] <= w[iq]))
+                    uint64_t a, b;
+                    if (wl <= wi) {
                         p0 = lq++;
-                    else
+                        a = wl;
+                        wl = lq < n ? w[lq] : INF;
+                    } else {
                         p0 = iq++;
-                    if (lq < n && (iq >= next || w[lq] <= w[iq]))
+                        a = wi;
+                        wi = iq < next ? w[iq] : INF;
+                    }
+                    if (wl <= wi) {
                         p1 = lq++;
-                    else
+                        b = wl;
+                        wl = lq < n ? w[lq] : INF;
+                    } else {
                         p1 = iq++;
-                    w[next] = w[p0] + w[p1];
+                        b = wi;
+                        wi = iq < next ? w[iq] : INF;
+                    }
+                    const uint64_t sum = a + b;
+                    w[next] = sum;
                     par[p0] = (int16_t)next;
                     par[p1] = (int16_t)next;
+                    if (iq == next)
+                        wi = sum; // the new node is the front of the empty merged queue
                     next++;
                 }
-                const int root = next - 1;
-                dep[root] = 0;
-                for (int v = root - 1; v >= 0; v--)
-                    dep[v] = (uint8_t)(dep[par[v]] + 1);
-                for (int i = 0; i < n; i++) {
-                    len[leafsym[i]] = dep[i];
-                    maxlen = max(maxlen, (int)dep[i]);
-                }
             }
-            s_maxlen = maxlen;
+            s_maxlen = 0;
+        }
+        __syncthreads();
+        if (n > 1 && t < n) {
+            // depth of leaf t: parent hops up to the root (node 2n-2)
+            int v = t, d = 0;
+            const int root = 2 * n - 2;
+            while (v != root) {
+                v = par[v];
+                d++;
+            }
+            len[leafsym[t]] = (uint8_t)min(d, 255);
+            atomicMax(&s_maxlen, d);
+        } else if (n == 1 && t == 0) {
+            s_maxlen = 1;
         }
         __syncthreads();
         if (s_maxlen <= kMaxCodeLen)
@@ -301,17 +362,25 @@ void launch_codebook(const Job *d_jobs, int njobs, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// Encoder. One wave per chunk; chunks are taken in increasing order from an
-// atomic counter. Each lane owns a contiguous run of the chunk's symbols; a
-// wave scan of codeword lengths gives every lane its bit offset, lanes OR
-// their bits into an LDS word buffer (shared boundary words with atomics),
-// and the wave stores the packed words coalesced. The chunk's payload offset
-// and its first outlier slot come from the look-back over preceding chunks,
-// so codes are read once and every section is written in place.
+// Encoder, in two passes over the codes.
+//  1. k_enc_sizes: a workgroup sizes 64 consecutive chunks (codeword bits and
+//     outliers per chunk), scans them, and takes one decoupled look-back over
+//     the preceding groups to turn them into each chunk's payload word offset
+//     and first outlier slot; it also writes the stream's chunk table and,
+//     for the last group, the payload size and total stream size.
+//  2. k_enc_pack: one wave per chunk, no waiting. Each lane owns a contiguous
+//     run of the chunk's symbols; a wave scan of codeword lengths gives every
+//     lane its bit offset, lanes OR their bits into an LDS word buffer (words
+//     shared with a neighbour lane via LDS atomics), and the wave stores the
+//     packed words coalesced at the chunk's offset. Outliers (code 0) are
+//     written with their exact values at their slots.
+// The codes are read twice; the second read mostly hits the L2/MALL and
+// keeps the packing free of any cross-chunk dependency.
 // ---------------------------------------------------------------------------
-constexpr int kEncSeg = 1024;            // symbols packed per pass
-constexpr int kEncBuf = kEncSeg + 2;     // words of the LDS pack buffer
+constexpr int kEncSeg = 1024;        // symbols packed per pass of a wave
+constexpr int kEncBuf = kEncSeg + 2; // words of a wave's LDS pack buffer
 constexpr int kEncWaves = 4;
+constexpr int kGroupChunks = kEncGroupChunks;
 
 __device__ inline void load_lane_codes(const uint8_t *__restrict__ src, int P, int n,
                                        uint32_t r[4])
@@ -337,8 +406,107 @@ __device__ inline uint32_t code_at(const uint32_t r[4], int k)
     return (w >> (8 * (k & 3))) & 255u;
 }
 
-__global__ __launch_bounds__(256) void k_encode(const Job *__restrict__ jobs, int njobs,
-                                                uint64_t total, Counters *cnt)
+// Bits and outliers of one lane's share of a segment.
+__device__ inline void lane_sizes(const uint32_t r[4], int n, const uint8_t *len, uint32_t &bits,
+                                  uint32_t &zeros)
+{
+    bits = 0;
+    zeros = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        if (k < n) {
+            const uint32_t c = code_at(r, k);
+            bits += len[c];
+            zeros += (c == 0);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs, int njobs,
+                                                   uint64_t total, Counters *cnt)
+{
+    __shared__ uint8_t len[256];
+    __shared__ uint32_t s_words[kGroupChunks], s_zeros[kGroupChunks];
+    __shared__ uint32_t s_gid;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0)
+        s_gid = atomicAdd(&cnt->enc_next, 1u);
+    __syncthreads();
+    const uint64_t gid = s_gid;
+    if (gid >= total)
+        return;
+    const Job &J = jobs[find_job<WK_GROUP>(jobs, njobs, gid)];
+    FieldState *st = J.st;
+    if (st->flags & (ST_CONST | ST_NONFINITE))
+        return; // every group of this field returns here: nobody waits on it
+    len[t] = st->cb_len[t];
+    __syncthreads();
+    const uint64_t g = gid - J.group_begin;
+    const uint64_t cfirst = g * kGroupChunks;
+    const int nc = (int)min<uint64_t>(kGroupChunks, J.n_chunks - cfirst);
+    for (int k = 0; k < kGroupChunks / kEncWaves; k++) {
+        const int lc = wv * (kGroupChunks / kEncWaves) + k;
+        if (lc >= nc)
+            break;
+        const uint64_t ck = cfirst + lc;
+        const uint64_t c0 = ck << J.log2_chunk;
+        const int clen = (int)(min(c0 + J.chunk, J.N) - c0);
+        uint64_t bits = 0;
+        uint32_t zeros = 0;
+        for (int sg = 0; sg * kEncSeg < clen; sg++) {
+            const int sl = min(kEncSeg, clen - sg * kEncSeg);
+            const int P = (sl + 63) / 64;
+            const int n = max(0, min(P, sl - lane * P));
+            uint32_t r[4], b, z;
+            load_lane_codes(J.codes + c0 + sg * kEncSeg + lane * P, P, n, r);
+            lane_sizes(r, n, len, b, z);
+            bits += b;
+            zeros += z;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            bits += shfl64(bits, lane ^ o);
+            zeros += (uint32_t)__shfl_xor((int)zeros, o, 64);
+        }
+        if (lane == 0) {
+            s_words[lc] = (uint32_t)((bits + 31) >> 5);
+            s_zeros[lc] = zeros;
+        }
+    }
+    __syncthreads();
+    if (wv != 0)
+        return;
+    const uint64_t w = lane < nc ? s_words[lane] : 0;
+    const uint64_t z = lane < nc ? s_zeros[lane] : 0;
+    const uint64_t wi = wave_incl_scan64(w), zi = wave_incl_scan64(z);
+    const uint64_t gw = shfl64(wi, 63), gz = shfl64(zi, 63);
+    const uint64_t wbase = lookback(J.lb_a, g, gw);
+    const uint64_t zbase = lookback(J.lb_b, g, gz);
+    const uint64_t cap = J.cap;
+    if (lane < nc) {
+        const uint64_t ck = cfirst + lane;
+        J.woff[ck] = wbase + wi - w;
+        J.zoff[ck] = zbase + zi - z;
+        if (kOffChunks + 4 * (ck + 1) <= cap)
+            reinterpret_cast<uint32_t *>(J.stream + kOffChunks)[ck] = (uint32_t)w;
+    }
+    if (lane == 0 && cfirst + nc == J.n_chunks) {
+        const uint64_t pw = wbase + gw;
+        const uint64_t total_bytes = st->off_payload + 4 * pw;
+        st->payload_words = pw;
+        st->total_bytes = total_bytes;
+        if (H_TOTAL + 8 <= cap) {
+            *reinterpret_cast<uint64_t *>(J.stream + H_PWORDS) = pw;
+            *reinterpret_cast<uint64_t *>(J.stream + H_TOTAL) = total_bytes;
+        }
+        if (total_bytes > cap)
+            atomicOr(&st->flags, (uint32_t)ST_OVERFLOW);
+        if (zbase + gz != st->n_out)
+            atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, int njobs,
+                                                  uint64_t total)
 {
     __shared__ uint32_t s_code[kEncWaves][256];
     __shared__ uint8_t s_len[kEncWaves][256];
@@ -350,13 +518,8 @@ __global__ __launch_bounds__(256) void k_encode(const Job *__restrict__ jobs, in
     for (int k = lane; k < kEncBuf; k += 64)
         buf[k] = 0;
     int cur = -1;
-    for (;;) {
-        uint32_t id = 0;
-        if (lane == 0)
-            id = atomicAdd(&cnt->enc_next, 1u);
-        id = (uint32_t)__shfl((int)id, 0, 64);
-        if (id >= total)
-            break;
+    for (uint64_t id = (uint64_t)blockIdx.x * kEncWaves + wv; id < total;
+         id += (uint64_t)gridDim.x * kEncWaves) {
         const int ji = find_job<WK_CHUNK>(jobs, njobs, id);
         const Job &J = jobs[ji];
         FieldState *st = J.st;
@@ -372,77 +535,36 @@ __global__ __launch_bounds__(256) void k_encode(const Job *__restrict__ jobs, in
         }
         const uint64_t ck = id - J.chunk_begin;
         const uint64_t c0 = ck << J.log2_chunk;
-        const uint64_t c1 = min(c0 + J.chunk, J.N);
-        const int clen = (int)(c1 - c0);
-        const int nseg = (clen + kEncSeg - 1) / kEncSeg;
+        const int clen = (int)(min(c0 + J.chunk, J.N) - c0);
         const uint8_t *src = J.codes + c0;
-
-        // pass 1: chunk totals (bits, outliers)
-        uint32_t r[4];
-        uint64_t lbits = 0;
-        uint32_t lzero = 0;
-        for (int sg = 0; sg < nseg; sg++) {
-            const int sl = min(kEncSeg, clen - sg * kEncSeg);
-            const int P = (sl + 63) / 64;
-            const int n = max(0, min(P, sl - lane * P));
-            load_lane_codes(src + sg * kEncSeg + lane * P, P, n, r);
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                if (k < n) {
-                    const uint32_t c = code_at(r, k);
-                    lbits += len[c];
-                    lzero += (c == 0);
-                }
-            }
-        }
-        uint64_t tbits = lbits;
-        uint32_t tzero = lzero;
-        for (int o = 32; o > 0; o >>= 1) {
-            tbits += shfl64(tbits, lane ^ o);
-            tzero += (uint32_t)__shfl_xor((int)tzero, o, 64);
-        }
-        const uint64_t twords = (tbits + 31) >> 5;
-        uint64_t excl = 0;
-        if (lane < 2)
-            excl = lookback(lane == 0 ? J.lb_a : J.lb_b, ck, lane == 0 ? twords : (uint64_t)tzero);
-        const uint64_t wbase = shfl64(excl, 0);
-        const uint64_t obase = shfl64(excl, 1);
-
+        const uint64_t wbase = J.woff[ck];
+        uint64_t zpos0 = J.zoff[ck];
         const uint64_t cap = J.cap;
         uint32_t *payload = reinterpret_cast<uint32_t *>(J.stream + st->off_payload);
-        const uint64_t pay_words_cap =
-            cap > st->off_payload ? (cap - st->off_payload) / 4 : 0;
+        const uint64_t pay_words_cap = cap > st->off_payload ? (cap - st->off_payload) / 4 : 0;
         const uint64_t o_idx = st->off_oidx, o_val = st->off_oval;
         const int ib = J.idx_bytes;
-
-        // pass 2: pack segment by segment
-        uint64_t sb = 0;      // chunk-relative bit at the segment start
-        uint64_t zrun = 0;    // outliers before the segment
-        for (int sg = 0; sg < nseg; sg++) {
+        uint64_t sb = 0; // chunk-relative bit at the segment start
+        for (int sg = 0; sg * kEncSeg < clen; sg++) {
             const int sl = min(kEncSeg, clen - sg * kEncSeg);
             const int P = (sl + 63) / 64;
             const int n = max(0, min(P, sl - lane * P));
             const uint64_t gfirst = c0 + (uint64_t)sg * kEncSeg + (uint64_t)lane * P;
+            uint32_t r[4], mb, mz;
             load_lane_codes(src + sg * kEncSeg + lane * P, P, n, r);
-            uint32_t mb = 0, mz = 0;
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                if (k < n) {
-                    const uint32_t c = code_at(r, k);
-                    mb += len[c];
-                    mz += (c == 0);
-                }
-            }
+            lane_sizes(r, n, len, mb, mz);
             const uint32_t ib_incl = wave_incl_scan(mb);
             const uint32_t iz_incl = wave_incl_scan(mz);
             const uint32_t seg_bits = (uint32_t)__shfl((int)ib_incl, 63, 64);
             const uint32_t seg_zero = (uint32_t)__shfl((int)iz_incl, 63, 64);
             const uint64_t wb = sb >> 5;
-            // bit offset of this lane relative to word wb
-            uint32_t orel = (uint32_t)(sb & 31) + (ib_incl - mb);
+            const uint32_t orel = (uint32_t)(sb & 31) + (ib_incl - mb);
             uint32_t cw = orel >> 5, sh = orel & 31, curw = 0;
-            uint64_t zpos = obase + zrun + (iz_incl - mz);
-            for (int k = 0; k < n; k++) {
+            uint64_t zpos = zpos0 + (iz_incl - mz);
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                if (k >= n)
+                    break;
                 const uint32_t c = code_at(r, k);
                 const uint32_t L = len[c], cd = code[c];
                 if (sh + L < 32) {
@@ -494,9 +616,8 @@ __global__ __launch_bounds__(256) void k_encode(const Job *__restrict__ jobs, in
                 buf[0] = partial;
             wave_sync_lds();
             sb = se;
-            zrun += seg_zero;
+            zpos0 += seg_zero;
         }
-        // last partial word of the chunk
         if (lane == 0) {
             if (sb & 31) {
                 const uint64_t gw = wbase + (sb >> 5);
@@ -504,42 +625,28 @@ __global__ __launch_bounds__(256) void k_encode(const Job *__restrict__ jobs, in
                     payload[gw] = buf[0];
             }
             buf[0] = 0;
-            if (kOffChunks + 4 * (ck + 1) <= cap)
-                reinterpret_cast<uint32_t *>(J.stream + kOffChunks)[ck] = (uint32_t)twords;
-            if (ck == J.n_chunks - 1) {
-                const uint64_t pw = wbase + twords;
-                const uint64_t total_bytes = st->off_payload + 4 * pw;
-                st->payload_words = pw;
-                st->total_bytes = total_bytes;
-                if (H_TOTAL + 8 <= cap) {
-                    *reinterpret_cast<uint64_t *>(J.stream + H_PWORDS) = pw;
-                    *reinterpret_cast<uint64_t *>(J.stream + H_TOTAL) = total_bytes;
-                }
-                if (total_bytes > cap)
-                    atomicOr(&st->flags, (uint32_t)ST_OVERFLOW);
-                if (obase + tzero != st->n_out)
-                    atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
-            }
         }
         wave_sync_lds();
     }
 }
 
-void launch_encode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, int grid,
-                   hipStream_t s)
+void launch_encode(const Job *d_jobs, int njobs, uint64_t total_chunks, uint64_t total_groups,
+                   Counters *cnt, int grid, hipStream_t s)
 {
-    if (total == 0)
+    if (total_chunks == 0)
         return;
-    uint64_t need = cdiv(total, kEncWaves);
+    hipLaunchKernelGGL(k_enc_sizes, dim3((uint32_t)total_groups), dim3(256), 0, s, d_jobs, njobs,
+                       total_groups, cnt);
+    uint64_t need = cdiv(total_chunks, kEncWaves);
     uint64_t g = need < (uint64_t)grid ? need : (uint64_t)grid;
-    hipLaunchKernelGGL(k_encode, dim3((uint32_t)g), dim3(64 * kEncWaves), 0, s, d_jobs, njobs,
-                       total, cnt);
+    hipLaunchKernelGGL(k_enc_pack, dim3((uint32_t)g), dim3(64 * kEncWaves), 0, s, d_jobs, njobs,
+                       total_chunks);
 }
 
 int encode_blocks_per_cu()
 {
     int n = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_encode, 64 * kEncWaves, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_enc_pack, 64 * kEncWaves, 0);
     return n > 0 ? n : 1;
 }
 
@@ -647,6 +754,7 @@ void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s)
 // payload offset by look-back over the stored word counts, and each thread
 // decodes its chunk sequentially with the LDS lookup table.
 constexpr int kDecChunks = 256;
+constexpr int kWin = 32; // payload words per refill of a decoder's LDS window
 
 __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, int njobs,
                                                 uint64_t total, Counters *cnt)
@@ -657,6 +765,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     __shared__ uint32_t s_id, s_maxlen;
     __shared__ uint64_t s_wsum[4];
     __shared__ uint64_t s_base;
+    __shared__ uint32_t s_win[kDecChunks * (kWin + 1)];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (t == 0)
         s_id = atomicAdd(&cnt->dec_next, 1u);
@@ -694,8 +803,11 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         before += (k < wv) ? s_wsum[k] : 0;
         blk_total += s_wsum[k];
     }
-    if (t == 0)
-        s_base = lookback(J.lb_a, lb, blk_total);
+    if (wv == 0) {
+        const uint64_t b = lookback(J.lb_a, lb, blk_total);
+        if (lane == 0)
+            s_base = b;
+    }
     __syncthreads();
     if (chunk >= J.n_chunks)
         return;
@@ -711,8 +823,13 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     const uint32_t *words = reinterpret_cast<const uint32_t *>(J.stream + J.off_payload);
     const uint64_t i0 = chunk << J.log2_chunk, i1 = min(i0 + J.chunk, J.N);
     const uint32_t maxlen = s_maxlen;
-    uint64_t wpos = start;
     const uint64_t wend = start + wc;
+    // payload words reach the decoder through a per-thread LDS window refilled
+    // with kWin independent loads at a time, so the sequential decode waits for
+    // memory once per window rather than once per word
+    uint32_t *mywin = s_win + t * (kWin + 1);
+    uint64_t wnext = start;
+    int wi = kWin;
     uint64_t buf = 0;
     int nb = 0;
     uint64_t used = 0;
@@ -721,8 +838,18 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     uint64_t i = i0;
     for (; i < i1; i++) {
         if (nb < 32) {
-            const uint32_t wd = wpos < wend ? words[wpos] : 0u;
-            wpos++;
+            if (wi == kWin) {
+                uint32_t r[kWin];
+#pragma unroll
+                for (int j = 0; j < kWin; j++)
+                    r[j] = wnext + j < wend ? words[wnext + j] : 0u;
+#pragma unroll
+                for (int j = 0; j < kWin; j++)
+                    mywin[j] = r[j];
+                wnext += kWin;
+                wi = 0;
+            }
+            const uint32_t wd = mywin[wi++];
             buf |= (uint64_t)wd << (32 - nb);
             nb += 32;
         }

@@ -16,6 +16,8 @@
 // workgroup and flushed once.
 #include "hiz_internal.h"
 
+#include <type_traits>
+
 namespace hiz {
 
 __constant__ int8_t c_perm_i[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
@@ -40,81 +42,91 @@ struct QParams {
     float eps, two_eb, inv;
 };
 
-// 1-D spline stencil (Sec. 5.1.2) along a line of LDS stride `st` at index li.
-__device__ __forceinline__ float stencil_lds(const float *__restrict__ v, int li, int st, int s,
-                                             bool pa, bool pc, bool pd, bool cub, int &rank)
+// Compile-time loop over I = B..E-1 (each iteration sees a constant index).
+template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f)
 {
-    const float b = v[li - s * st];
-    if (cub && pa && pc && pd) {
-        const float a = v[li - 3 * s * st], c = v[li + s * st], d = v[li + 3 * s * st];
-        rank = 4;
-        return ((b + c) * 9.0f - (a + d)) * 0.0625f;
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
     }
-    if (cub && pc && pd) {
-        const float c = v[li + s * st], d = v[li + 3 * s * st];
-        rank = 3;
-        return ((b * 3.0f + c * 6.0f) - d) * 0.125f;
-    }
-    if (cub && pa && pc) {
-        const float a = v[li - 3 * s * st], c = v[li + s * st];
-        rank = 3;
-        return ((b * 6.0f + c * 3.0f) - a) * 0.125f;
-    }
-    if (pc) {
-        const float c = v[li + s * st];
-        rank = 2;
-        return (b + c) * 0.5f;
-    }
-    if (pa) {
-        const float a = v[li - 3 * s * st];
-        rank = 1;
-        return b * 1.5f - a * 0.5f;
-    }
-    rank = 0;
-    return b;
 }
 
-// Prediction of target (x,y,z) at stride S with odd-axis mask M.
-// axis < 0: multi-dimensional scheme (mean of the highest-order predictions
-// along the axes of M, in x, y, z order); otherwise 1-D along `axis`.
-template <int TZ, int S, int M>
-__device__ __forceinline__ float predict(const float *__restrict__ v, int li, int x, int y, int z,
-                                         const Geo &g, int axis, bool cub)
+// 1-D spline stencil (Sec. 5.1.2) from the samples a = v(t-3s), b = v(t-s),
+// c = v(t+s), d = v(t+3s): Lagrange weights at the midpoint; where samples are
+// missing the order drops to quadratic (one side), linear, linear
+// extrapolation or copy. Rank: 4 cubic, 3 quadratic, 2 linear, 1 extrapolation,
+// 0 copy. Presence known at compile time (interior of full blocks).
+template <bool CUB, bool PA, bool PC, bool PD>
+__device__ __forceinline__ float stencil_ct(float a, float b, float c, float d, int &rank)
 {
-    using TS = TileShape<TZ>;
-    float px = 0.f, py = 0.f, pz = 0.f;
-    int rx = -1, ry = -1, rz = -1;
-    const bool want_x = (M & 1) && (axis < 0 || axis == 0);
-    const bool want_y = (M & 2) && (axis < 0 || axis == 1);
-    const bool want_z = (M & 4) && (axis < 0 || axis == 2);
-    if (want_x)
-        px = stencil_lds(v, li, TS::PX, S, x >= 3 * S, x + S < g.ex, x + 3 * S < g.ex, cub, rx);
-    if (want_y)
-        py = stencil_lds(v, li, TS::PZ, S, y >= 3 * S, y + S < g.ey, y + 3 * S < g.ey, cub, ry);
-    if (want_z) {
-        // z stencils stop at the faces of the target's own block
-        const int hi = min((z & ~15) + 16, g.ez - 1);
-        pz = stencil_lds(v, li, 1, S, (z & 15) >= 3 * S, z + S <= hi, z + 3 * S <= hi, cub, rz);
+    if constexpr (CUB && PA && PC && PD) {
+        rank = 4;
+        return ((b + c) * 9.0f - (a + d)) * 0.0625f;
+    } else if constexpr (CUB && !PA && PC && PD) {
+        rank = 3;
+        return ((b * 3.0f + c * 6.0f) - d) * 0.125f;
+    } else if constexpr (CUB && PA && PC && !PD) {
+        rank = 3;
+        return ((b * 6.0f + c * 3.0f) - a) * 0.125f;
+    } else if constexpr (PC) {
+        rank = 2;
+        return (b + c) * 0.5f;
+    } else if constexpr (PA) {
+        rank = 1;
+        return b * 1.5f - a * 0.5f;
+    } else {
+        rank = 0;
+        return b;
     }
-    if (axis >= 0)
-        return axis == 0 ? px : (axis == 1 ? py : pz);
-    if (M == 1)
+}
+
+// The same stencil with presence known only at run time, evaluated without
+// branches (every candidate is formed, the applicable one selected; samples
+// that are missing are never selected).
+template <bool CUB>
+__device__ __forceinline__ float stencil_rt(float a, float b, float c, float d, bool pa, bool pc,
+                                            bool pd, int &rank)
+{
+    const float vl = (b + c) * 0.5f;
+    const float ve = b * 1.5f - a * 0.5f;
+    float v = pc ? vl : (pa ? ve : b);
+    int r = pc ? 2 : (pa ? 1 : 0);
+    if constexpr (CUB) {
+        const float vc = ((b + c) * 9.0f - (a + d)) * 0.0625f;
+        const float vqr = ((b * 3.0f + c * 6.0f) - d) * 0.125f;
+        const float vql = ((b * 6.0f + c * 3.0f) - a) * 0.125f;
+        const bool full = pa && pc && pd, right = !pa && pc && pd, left = pa && pc && !pd;
+        v = full ? vc : (right ? vqr : (left ? vql : v));
+        r = full ? 4 : ((right || left) ? 3 : r);
+    }
+    rank = r;
+    return v;
+}
+
+// Multi-dimensional combination over the odd axes in mask M: keep the
+// predictions of the highest rank and average them in x, y, z order.
+template <int M>
+__device__ __forceinline__ float md_combine(float px, float py, float pz, int rx, int ry, int rz)
+{
+    if constexpr (M == 1)
         return px;
-    if (M == 2)
+    else if constexpr (M == 2)
         return py;
-    if (M == 4)
+    else if constexpr (M == 4)
         return pz;
-    const int best = max(rx, max(ry, rz));
-    const bool ux = (M & 1) && rx == best, uy = (M & 2) && ry == best,
-               uz = (M & 4) && rz == best;
-    const int m = (int)ux + (int)uy + (int)uz;
-    const float first = ux ? px : (uy ? py : pz);
-    const float second = ux ? (uy ? py : pz) : pz;
-    if (m == 1)
-        return first;
-    if (m == 2)
-        return (first + second) * 0.5f;
-    return ((px + py) + pz) / 3.0f;
+    else {
+        const int best = max((M & 1) ? rx : -1, max((M & 2) ? ry : -1, (M & 4) ? rz : -1));
+        const bool ux = (M & 1) && rx == best, uy = (M & 2) && ry == best,
+                   uz = (M & 4) && rz == best;
+        const int m = (int)ux + (int)uy + (int)uz;
+        const float first = ux ? px : (uy ? py : pz);
+        const float second = ux ? (uy ? py : pz) : pz;
+        if (m == 1)
+            return first;
+        if (m == 2)
+            return (first + second) * 0.5f;
+        return ((px + py) + pz) / 3.0f;
+    }
 }
 
 // Linear-scaling quantization (code = 128 + q, |q| <= 127; else outlier code 0
@@ -122,110 +134,327 @@ __device__ __forceinline__ float predict(const float *__restrict__ v, int li, in
 // FP32 rounding of the reconstruction.
 __device__ __forceinline__ uint8_t quantize(float xv, float p, const QParams &q, float &xo)
 {
+    // the same operations as the definition, evaluated without branches
     const float diff = xv - p;
     const float qf = diff * q.inv;
     const float qr = rintf(qf);
-    uint8_t code = 0;
-    xo = xv;
-    if (fabsf(qr) <= 127.0f) {
-        const int qi = (int)qr;
-        const float xr = p + ((float)qi * q.two_eb);
-        if (fabs((double)xv - (double)xr) <= (double)q.eps) {
-            code = (uint8_t)(qi + 128);
-            xo = xr;
-        }
-    }
-    return code;
+    const bool inrange = fabsf(qr) <= 127.0f;
+    const int qi = (int)(inrange ? qr : 0.0f);
+    const float xr = p + ((float)qi * q.two_eb);
+    const bool ok = inrange && fabs((double)xv - (double)xr) <= (double)q.eps;
+    xo = ok ? xr : xv;
+    return ok ? (uint8_t)(qi + 128) : (uint8_t)0;
 }
 
-// One pattern of a sub-step: targets whose odd-axis mask is M at stride S.
-template <int TZ, int S, int M, bool COMP>
-__device__ __forceinline__ void pattern(float *__restrict__ v, uint8_t *__restrict__ cb,
-                                        const uint8_t *__restrict__ cl, const Geo &g, int axis,
-                                        bool cub, const QParams &q)
+// 1-D stencil across the line direction at LDS index li along an axis of
+// stride st, for a target whose coordinate on that axis is `c` in a block
+// spanning [lo, hi] on that axis (run-time presence; branch-free).
+template <bool CUB, bool FULL>
+__device__ __forceinline__ float cross_stencil(const float *__restrict__ v, int li, int st, int c,
+                                               int lo, int hi, int S, int &rank)
+{
+    const bool pa = c - 3 * S >= lo, pc = FULL || c + S <= hi, pd = c + 3 * S <= hi;
+    const float b = v[li - S * st];
+    const float a = v[pa ? li - 3 * S * st : li - S * st];
+    const int ic = pc ? li + S * st : li - S * st;
+    const float cc = v[ic];
+    const float d = v[pd ? li + 3 * S * st : ic];
+    if constexpr (FULL) {
+        // inside a full block a target always has its +s neighbour
+        const float vl = (b + cc) * 0.5f;
+        if constexpr (CUB) {
+            const float vc = ((b + cc) * 9.0f - (a + d)) * 0.0625f;
+            const float vqr = ((b * 3.0f + cc * 6.0f) - d) * 0.125f;
+            const float vql = ((b * 6.0f + cc * 3.0f) - a) * 0.125f;
+            const float v1 = pa ? vql : vl;
+            const float v2 = pa ? vc : vqr;
+            rank = pd ? (pa ? 4 : 3) : (pa ? 3 : 2);
+            return pd ? v2 : v1;
+        } else {
+            rank = 2;
+            return vl;
+        }
+    } else {
+        return stencil_rt<CUB>(a, b, cc, d, pa, pc, pd, rank);
+    }
+}
+
+// One line of targets: along axis A (0 x, 1 y, 2 z) at stride S inside one
+// block, through (x0, y0, z0) whose A-coordinate is the block start; the
+// targets sit at odd multiples of S along A, the knowns at even multiples.
+// The four samples of the line stencil slide along the line in registers, so
+// each target costs one new LDS read plus, for the multi-dimensional scheme,
+// stencils along the other odd axes (MB/MC: the first/second other axis in
+// x, y, z order is odd and used). nA: extent of the block along A (17 for
+// full blocks). The stride is a run-time value so that one compact code path
+// serves every level.
+template <int TZ, int A, int MB, int MC, bool CUB, bool COMP, bool FULL>
+__device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restrict__ cb,
+                                        const uint8_t *__restrict__ cl, const Geo &g, int x0,
+                                        int y0, int z0, int nA, int S, const QParams &q)
 {
     using TS = TileShape<TZ>;
-    constexpr int CX = (M & 1) ? 8 / S : 8 / S + 1;
-    constexpr int CY = (M & 2) ? 8 / S : 8 / S + 1;
-    constexpr int CZ = (M & 4) ? 8 * TZ / S : 8 * TZ / S + 1;
-    constexpr int TOT = CX * CY * CZ;
-    for (int i = threadIdx.x; i < TOT; i += blockDim.x) {
-        const int iz = i % CZ, r = i / CZ, iy = r % CY, ix = r / CY;
-        const int x = ((M & 1) ? 2 * ix + 1 : 2 * ix) * S;
-        const int y = ((M & 2) ? 2 * iy + 1 : 2 * iy) * S;
-        const int z = ((M & 4) ? 2 * iz + 1 : 2 * iz) * S;
-        if (x >= g.ex || y >= g.ey || z >= g.ez)
-            continue;
-        const int li = x * TS::PX + y * TS::PZ + z;
-        const float p = predict<TZ, S, M>(v, li, x, y, z, g, axis, cub);
-        if (COMP) {
+    constexpr int B = (A == 0) ? 1 : 0;
+    constexpr int C = (A == 2) ? 1 : 2;
+    constexpr int stA = A == 0 ? TS::PX : (A == 1 ? TS::PZ : 1);
+    constexpr int stB = B == 0 ? TS::PX : TS::PZ;
+    constexpr int stC = C == 1 ? TS::PZ : 1;
+    constexpr int M = (1 << A) | (MB << B) | (MC << C);
+    const int K = 8 / S;
+    const int last = nA - 1;
+    const int li0 = x0 * TS::PX + y0 * TS::PZ + z0;
+    // block bounds of the cross axes
+    const int cB = B == 0 ? x0 : y0;
+    const int cC = C == 1 ? y0 : z0;
+    const int hiB = (B == 0 ? g.ex : g.ey) - 1;
+    int loC = 0, hiC;
+    if constexpr (C == 2) {
+        loC = cC & ~15;
+        hiC = min(loC + 16, g.ez - 1);
+    } else {
+        hiC = g.ey - 1;
+    }
+    float a = 0.f;
+    float b = v[li0];
+    float c = v[li0 + min(2 * S, last) * stA];
+    float d = v[li0 + min(4 * S, last) * stA];
+#pragma unroll 1
+    for (int k = 0; k < K; k++) {
+        const int tpos = (2 * k + 1) * S;
+        if (!FULL && tpos > last)
+            break;
+        const int li = li0 + tpos * stA;
+        const bool pa = k > 0, pc = FULL || (2 * k + 2) * S <= last,
+                   pd = (2 * k + 4) * S <= last;
+        int rA;
+        float pA;
+        if (CUB && pa && pc && pd) {
+            rA = 4;
+            pA = ((b + c) * 9.0f - (a + d)) * 0.0625f;
+        } else {
+            pA = stencil_rt<CUB>(a, b, c, d, pa, pc, pd, rA);
+        }
+        float p;
+        if constexpr (M == (1 << A)) {
+            p = pA;
+        } else {
+            float pB = 0.f, pC = 0.f;
+            int rB = -1, rC = -1;
+            if constexpr (MB)
+                pB = cross_stencil<CUB, FULL>(v, li, stB, cB, 0, hiB, S, rB);
+            if constexpr (MC)
+                pC = cross_stencil<CUB, FULL>(v, li, stC, cC, loC, hiC, S, rC);
+            const float px = A == 0 ? pA : pB;
+            const int rx = A == 0 ? rA : rB;
+            const float py = A == 1 ? pA : (B == 1 ? pB : pC);
+            const int ry = A == 1 ? rA : (B == 1 ? rB : rC);
+            const float pz = A == 2 ? pA : pC;
+            const int rz = A == 2 ? rA : rC;
+            p = md_combine<M>(px, py, pz, rx, ry, rz);
+        }
+        // slide the window: the next target's +3s sample
+        a = b;
+        b = c;
+        c = d;
+        d = v[li0 + min((2 * k + 6) * S, last) * stA];
+        const int x = A == 0 ? tpos : x0;
+        const int y = A == 1 ? tpos : y0;
+        const int z = A == 2 ? z0 + tpos : z0;
+        if constexpr (COMP) {
             float xo;
             const uint8_t code = quantize(v[li], p, q, xo);
             v[li] = xo;
-            if (x < g.ownx && y < g.owny && z < g.ownz)
-                cb[(x * 16 + y) * TS::OZ + z] = code;
+            const bool own = x < g.ownx && y < g.owny && z < g.ownz;
+            cb[own ? (x * 16 + y) * TS::OZ + z : TS::NC] = code;
         } else {
-            const uint8_t c = cl[li];
-            if (c != 0)
-                v[li] = p + ((float)((int)c - 128) * q.two_eb);
+            const uint8_t cc = cl[li];
+            if (cc != 0)
+                v[li] = p + ((float)((int)cc - 128) * q.two_eb);
+            // code 0: the exact outlier value is already in place
         }
     }
 }
 
-template <int TZ, int S, bool COMP>
-__device__ __forceinline__ void dispatch(int M, float *v, uint8_t *cb, const uint8_t *cl,
-                                         const Geo &g, int axis, bool cub, const QParams &q)
+enum : int { M_EVEN = 0, M_ODD = 1, M_ALL = 2 };
+
+__device__ __forceinline__ int mode_count(int mode, int n, int S)
 {
-    switch (M) {
-    case 1: pattern<TZ, S, 1, COMP>(v, cb, cl, g, axis, cub, q); break;
-    case 2: pattern<TZ, S, 2, COMP>(v, cb, cl, g, axis, cub, q); break;
-    case 3: pattern<TZ, S, 3, COMP>(v, cb, cl, g, axis, cub, q); break;
-    case 4: pattern<TZ, S, 4, COMP>(v, cb, cl, g, axis, cub, q); break;
-    case 5: pattern<TZ, S, 5, COMP>(v, cb, cl, g, axis, cub, q); break;
-    case 6: pattern<TZ, S, 6, COMP>(v, cb, cl, g, axis, cub, q); break;
-    default: pattern<TZ, S, 7, COMP>(v, cb, cl, g, axis, cub, q); break;
+    if (mode == M_EVEN)
+        return (n - 1) / (2 * S) + 1;
+    if (mode == M_ODD)
+        return n - 1 >= S ? (n - 1 - S) / (2 * S) + 1 : 0;
+    return (n - 1) / S + 1;
+}
+__device__ __forceinline__ int mode_coord(int mode, int i, int S)
+{
+    return mode == M_EVEN ? 2 * i * S : (mode == M_ODD ? (2 * i + 1) * S : i * S);
+}
+
+// quotient n / d for n, d < 2^16 with a multiply (m = ceil(2^32 / d))
+__device__ __forceinline__ uint32_t qdiv(uint32_t n, uint32_t d, uint32_t m)
+{
+    return d == 1 ? n : __umulhi(n, m);
+}
+__device__ __forceinline__ uint32_t qmagic(uint32_t d)
+{
+    return d <= 1 ? 0u : (uint32_t)(0xffffffffu / d + 1u);
+}
+
+// A group of lines of one kind: axis A plus which cross axes are odd and
+// interpolated (MD), with the coordinate modes of the two cross axes.
+struct LineGroup {
+    int kind;        // template instance, see run_line
+    int A, modeB, modeC;
+    int cntB, cntC, ncell, lines;
+    uint32_t mC, mBC; // magic multipliers for / cntC and / (cntB * cntC)
+};
+
+__device__ __forceinline__ LineGroup make_group(int kind, int A, int modeB, int modeC, int S,
+                                                const Geo &g, int TZ)
+{
+    LineGroup G;
+    G.kind = kind;
+    G.A = A;
+    G.modeB = modeB;
+    G.modeC = modeC;
+    const int nB = A == 0 ? g.ey : g.ex;
+    const int nC = A == 2 ? g.ey : g.ez;
+    G.cntB = mode_count(modeB, nB, S);
+    G.cntC = mode_count(modeC, nC, S);
+    if (A == 2)
+        G.ncell = g.ez - 1 >= S ? min(TZ, (g.ez - 1 - S) / 16 + 1) : 0;
+    else
+        G.ncell = 1;
+    if ((A == 0 && g.ex - 1 < S) || (A == 1 && g.ey - 1 < S))
+        G.ncell = 0;
+    G.lines = G.cntB * G.cntC * G.ncell;
+    G.mC = qmagic((uint32_t)G.cntC);
+    G.mBC = qmagic((uint32_t)(G.cntB * G.cntC));
+    return G;
+}
+
+// kinds: 0..2 plain lines along z, y, x; 3 along x with y odd (MD xy);
+// 4 along z with x odd (MD xz); 5 along z with y odd (MD yz); 6 along z with x
+// and y odd (MD xyz).
+template <int TZ, bool CUB, bool COMP, bool FULL>
+__device__ __forceinline__ void run_line(const LineGroup &G, int l, int S, float *v, uint8_t *cb,
+                                         const uint8_t *cl, const Geo &g, const QParams &q)
+{
+    const uint32_t nbc = (uint32_t)(G.cntB * G.cntC);
+    const uint32_t cell = qdiv((uint32_t)l, nbc, G.mBC);
+    const uint32_t rem = (uint32_t)l - cell * nbc;
+    const uint32_t iB = qdiv(rem, (uint32_t)G.cntC, G.mC);
+    const uint32_t iC = rem - iB * (uint32_t)G.cntC;
+    const int cB = mode_coord(G.modeB, (int)iB, S);
+    const int cC = mode_coord(G.modeC, (int)iC, S);
+    if (G.A == 2) {
+        const int z0 = 16 * (int)cell;
+        const int nA = FULL ? 17 : min(17, g.ez - z0);
+        switch (G.kind) {
+        case 0: do_line<TZ, 2, 0, 0, CUB, COMP, FULL>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
+        case 4: do_line<TZ, 2, 1, 0, CUB, COMP, FULL>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
+        case 5: do_line<TZ, 2, 0, 1, CUB, COMP, FULL>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
+        default: do_line<TZ, 2, 1, 1, CUB, COMP, FULL>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
+        }
+    } else if (G.A == 1) {
+        do_line<TZ, 1, 0, 0, CUB, COMP, FULL>(v, cb, cl, g, cB, 0, cC, FULL ? 17 : g.ey, S, q);
+    } else if (G.kind == 3) {
+        do_line<TZ, 0, 1, 0, CUB, COMP, FULL>(v, cb, cl, g, 0, cB, cC, FULL ? 17 : g.ex, S, q);
+    } else {
+        do_line<TZ, 0, 0, 0, CUB, COMP, FULL>(v, cb, cl, g, 0, cB, cC, FULL ? 17 : g.ex, S, q);
     }
 }
 
-// One level (stride S) in three sub-steps. MD: 1-D, then 2-D, then 3-D
-// targets. SEQ(order): pass j handles the targets whose last odd axis in the
-// order is the j-th, interpolating along that axis.
-template <int TZ, int S, bool COMP>
-__device__ void level(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g, const uint8_t *cfg,
-                      const QParams &q)
+// One level (stride S) in three sub-steps, each a set of line groups swept in
+// parallel by the workgroup, with a barrier between sub-steps.
+// MD: 1-D, then 2-D, then 3-D targets. SEQ(order): pass j interpolates along
+// the j-th axis of the order every target whose last odd axis (in that order)
+// is that axis; axes earlier in the order take every multiple of S, later
+// ones even multiples only.
+template <int TZ, bool CUB, bool COMP, bool FULL>
+__device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g,
+                                            int S, bool md, int perm, const QParams &q)
 {
-    const bool cub = cfg[0] != 0;
-    const bool md = cfg[1] == 0;
-    const int perm = cfg[2];
     for (int sub = 1; sub <= 3; sub++) {
-        for (int M = 1; M <= 7; M++) {
-            int axis = -1;
-            if (md) {
-                if (__popc(M) != sub)
-                    continue;
+        LineGroup G0, G1, G2;
+        int ng;
+        if (md) {
+            if (sub == 1) {
+                G0 = make_group(0, 2, M_EVEN, M_EVEN, S, g, TZ);
+                G1 = make_group(1, 1, M_EVEN, M_EVEN, S, g, TZ);
+                G2 = make_group(2, 0, M_EVEN, M_EVEN, S, g, TZ);
+                ng = 3;
+            } else if (sub == 2) {
+                G0 = make_group(3, 0, M_ODD, M_EVEN, S, g, TZ);
+                G1 = make_group(4, 2, M_ODD, M_EVEN, S, g, TZ);
+                G2 = make_group(5, 2, M_EVEN, M_ODD, S, g, TZ);
+                ng = 3;
             } else {
-                int last = -1;
-                for (int j = 0; j < 3; j++)
-                    if ((M >> c_perm_i[perm][j]) & 1)
-                        last = j;
-                if (last != sub - 1)
-                    continue;
-                axis = c_perm_i[perm][sub - 1];
+                G0 = make_group(6, 2, M_ODD, M_ODD, S, g, TZ);
+                G1 = G0;
+                G2 = G0;
+                ng = 1;
             }
-            dispatch<TZ, S, COMP>(M, v, cb, cl, g, axis, cub, q);
+        } else {
+            const int A = c_perm_i[perm][sub - 1];
+            const int B = A == 0 ? 1 : 0, C = A == 2 ? 1 : 2;
+            // an axis placed before A in the order may be odd or even
+            bool earlyB = false, earlyC = false;
+            for (int j = 0; j < sub - 1; j++) {
+                earlyB |= c_perm_i[perm][j] == B;
+                earlyC |= c_perm_i[perm][j] == C;
+            }
+            const int modeB = earlyB ? M_ALL : M_EVEN;
+            const int modeC = earlyC ? M_ALL : M_EVEN;
+            G0 = make_group(A == 2 ? 0 : (A == 1 ? 1 : 2), A, modeB, modeC, S, g, TZ);
+            G1 = G0;
+            G2 = G0;
+            ng = 1;
+        }
+        const int n0 = G0.lines;
+        const int n1 = n0 + (ng > 1 ? G1.lines : 0);
+        const int n2 = n1 + (ng > 2 ? G2.lines : 0);
+        for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+            if (i < n0)
+                run_line<TZ, CUB, COMP, FULL>(G0, i, S, v, cb, cl, g, q);
+            else if (i < n1)
+                run_line<TZ, CUB, COMP, FULL>(G1, i - n0, S, v, cb, cl, g, q);
+            else
+                run_line<TZ, CUB, COMP, FULL>(G2, i - n1, S, v, cb, cl, g, q);
         }
         __syncthreads();
     }
 }
 
 template <int TZ, bool COMP>
-__device__ void walk_levels(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g,
-                            const uint8_t (*cfg)[3], const QParams &q)
+__device__ __forceinline__ void level(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g, int S,
+                                      const uint8_t *cfg, const QParams &q)
 {
-    level<TZ, 8, COMP>(v, cb, cl, g, cfg[0], q);
-    level<TZ, 4, COMP>(v, cb, cl, g, cfg[1], q);
-    level<TZ, 2, COMP>(v, cb, cl, g, cfg[2], q);
-    level<TZ, 1, COMP>(v, cb, cl, g, cfg[3], q);
+    const bool cub = cfg[0] != 0;
+    const bool md = cfg[1] == 0;
+    const int perm = cfg[2];
+    const bool full = g.ex == kSide && g.ey == kSide && g.ez == 16 * TZ + 1;
+    if (cub) {
+        if (full)
+            level_lines<TZ, true, COMP, true>(v, cb, cl, g, S, md, perm, q);
+        else
+            level_lines<TZ, true, COMP, false>(v, cb, cl, g, S, md, perm, q);
+    } else {
+        if (full)
+            level_lines<TZ, false, COMP, true>(v, cb, cl, g, S, md, perm, q);
+        else
+            level_lines<TZ, false, COMP, false>(v, cb, cl, g, S, md, perm, q);
+    }
+}
+
+// Levels of stride 8, 4, 2, 1 in order (coarse to fine).
+template <int TZ, bool COMP>
+__device__ __forceinline__ void walk_levels(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g,
+                                            const uint8_t (*cfg)[3], const QParams &q)
+{
+#pragma unroll 1
+    for (int l = 0; l < kLevels; l++)
+        level<TZ, COMP>(v, cb, cl, g, 8 >> l, cfg[l], q);
 }
 
 // Tile u of job J -> geometry and global row offsets (into LDS `rowoff`).
@@ -269,6 +498,187 @@ __device__ __forceinline__ void xcd_range(uint64_t total, uint64_t &first, uint6
 }
 
 // ---------------------------------------------------------------------------
+// Tile I/O. Each thread issues all of its global loads before it writes any
+// of them to LDS, so a tile costs one memory round trip rather than one per
+// element. Rows are read as 16-byte pieces where the field's rows are
+// 16-byte aligned (dz a multiple of 4 for floats, of 16 for codes).
+// ---------------------------------------------------------------------------
+template <int TZ>
+__device__ __forceinline__ void load_tile_values(float *__restrict__ v,
+                                                 const float *__restrict__ field,
+                                                 const uint64_t *rowoff, const Geo &g, bool vec,
+                                                 bool track, uint32_t &kmn, uint32_t &kmx,
+                                                 bool &bad)
+{
+    using TS = TileShape<TZ>;
+    auto note = [&](float val) {
+        if (track) {
+            bad |= !isfinite(val);
+            const uint32_t k = fkey(val);
+            kmn = min(kmn, k);
+            kmx = max(kmx, k);
+        }
+    };
+    if (vec) {
+        constexpr int PIECES = 4 * TZ + 1; // 4*TZ float4 pieces and the face element
+        constexpr int ITEMS = TS::NROW * PIECES;
+        constexpr int BATCH = 4;           // pieces in flight per thread
+#pragma nounroll
+        for (int i0 = 0; i0 < ITEMS; i0 += 256 * BATCH) {
+            float4 buf[BATCH];
+#pragma unroll
+            for (int k = 0; k < BATCH; k++) {
+                const int i = i0 + threadIdx.x + 256 * k;
+                const int r = i / PIECES, pc = i - r * PIECES;
+                const int y = r % kSide, x = r / kSide;
+                buf[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (i < ITEMS && x < g.ex && y < g.ey) {
+                    const float *rp = field + rowoff[r];
+                    const int z0 = 4 * pc;
+                    if (pc < 4 * TZ && z0 + 4 <= g.ez)
+                        buf[k] = *reinterpret_cast<const float4 *>(rp + z0);
+                    else if (pc == 4 * TZ && 16 * TZ < g.ez)
+                        buf[k].x = rp[16 * TZ];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < BATCH; k++) {
+                const int i = i0 + threadIdx.x + 256 * k;
+                const int r = i / PIECES, pc = i - r * PIECES;
+                const int y = r % kSide, x = r / kSide;
+                if (i < ITEMS && x < g.ex && y < g.ey) {
+                    float *vp = v + x * TS::PX + y * TS::PZ;
+                    if (pc < 4 * TZ) {
+                        const int z0 = 4 * pc;
+                        if (z0 + 4 <= g.ez) {
+                            const float e[4] = {buf[k].x, buf[k].y, buf[k].z, buf[k].w};
+#pragma unroll
+                            for (int j = 0; j < 4; j++) {
+                                vp[z0 + j] = e[j];
+                                note(e[j]);
+                            }
+                        } else {
+                            // a row cut short by the field boundary (rare)
+                            for (int z = z0; z < g.ez; z++) {
+                                const float e = field[rowoff[r] + z];
+                                vp[z] = e;
+                                note(e);
+                            }
+                        }
+                    } else if (16 * TZ < g.ez) {
+                        vp[16 * TZ] = buf[k].x;
+                        note(buf[k].x);
+                    }
+                }
+            }
+        }
+    } else {
+        constexpr int NE = TS::NROW * TS::EZ;
+#pragma nounroll
+        for (int i0 = 0; i0 < NE; i0 += 256 * 8) {
+            float b[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int i = i0 + threadIdx.x + 256 * k;
+                const int z = i % TS::EZ, r = i / TS::EZ;
+                const int y = r % kSide, x = r / kSide;
+                b[k] = 0.f;
+                if (i < NE && x < g.ex && y < g.ey && z < g.ez)
+                    b[k] = field[rowoff[r] + z];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int i = i0 + threadIdx.x + 256 * k;
+                const int z = i % TS::EZ, r = i / TS::EZ;
+                const int y = r % kSide, x = r / kSide;
+                if (i < NE && x < g.ex && y < g.ey && z < g.ez) {
+                    v[x * TS::PX + y * TS::PZ + z] = b[k];
+                    note(b[k]);
+                }
+            }
+        }
+    }
+}
+
+// Codes of the whole tile region (with faces) into LDS.
+template <int TZ>
+__device__ __forceinline__ void load_tile_codes(uint8_t *__restrict__ cl,
+                                                const uint8_t *__restrict__ codes,
+                                                const uint64_t *rowoff, const Geo &g, bool vec)
+{
+    using TS = TileShape<TZ>;
+    if (vec) {
+        constexpr int PIECES = TZ + 1; // TZ 16-byte pieces and the face byte
+        constexpr int ITEMS = TS::NROW * PIECES;
+        constexpr int BATCH = 2;
+#pragma nounroll
+        for (int i0 = 0; i0 < ITEMS; i0 += 256 * BATCH) {
+            uint4 buf[BATCH];
+#pragma unroll
+            for (int k = 0; k < BATCH; k++) {
+                const int i = i0 + threadIdx.x + 256 * k;
+                const int r = i / PIECES, pc = i - r * PIECES;
+                const int y = r % kSide, x = r / kSide;
+                buf[k] = make_uint4(0, 0, 0, 0);
+                if (i < ITEMS && x < g.ex && y < g.ey) {
+                    const uint8_t *rp = codes + rowoff[r];
+                    const int z0 = 16 * pc;
+                    if (pc < TZ && z0 + 16 <= g.ez)
+                        buf[k] = *reinterpret_cast<const uint4 *>(rp + z0);
+                    else if (pc == TZ && z0 < g.ez)
+                        buf[k].x = rp[z0];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < BATCH; k++) {
+                const int i = i0 + threadIdx.x + 256 * k;
+                const int r = i / PIECES, pc = i - r * PIECES;
+                const int y = r % kSide, x = r / kSide;
+                if (i < ITEMS && x < g.ex && y < g.ey) {
+                    uint8_t *cp = cl + x * TS::PX + y * TS::PZ + 16 * pc;
+                    const int z0 = 16 * pc;
+                    if (pc < TZ && z0 + 16 <= g.ez) {
+                        const uint32_t w[4] = {buf[k].x, buf[k].y, buf[k].z, buf[k].w};
+#pragma unroll
+                        for (int j = 0; j < 16; j++)
+                            cp[j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+                    } else if (pc < TZ) {
+                        // a row cut short by the field boundary (rare)
+                        for (int z = z0; z < g.ez; z++)
+                            cp[z - z0] = codes[rowoff[r] + z];
+                    } else if (z0 < g.ez) {
+                        cp[0] = (uint8_t)buf[k].x;
+                    }
+                }
+            }
+        }
+    } else {
+        constexpr int NE = TS::NROW * TS::EZ;
+#pragma nounroll
+        for (int i0 = 0; i0 < NE; i0 += 256 * 8) {
+            uint8_t b[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int i = i0 + threadIdx.x + 256 * k;
+                const int z = i % TS::EZ, r = i / TS::EZ;
+                const int y = r % kSide, x = r / kSide;
+                b[k] = 0;
+                if (i < NE && x < g.ex && y < g.ey && z < g.ez)
+                    b[k] = codes[rowoff[r] + z];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int i = i0 + threadIdx.x + 256 * k;
+                const int z = i % TS::EZ, r = i / TS::EZ;
+                const int y = r % kSide, x = r / kSide;
+                if (i < NE && x < g.ex && y < g.ey && z < g.ez)
+                    cl[x * TS::PX + y * TS::PZ + z] = b[k];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Compression: predict + quantize + histogram, persistent over tiles.
 // ---------------------------------------------------------------------------
 template <int TZ>
@@ -277,12 +687,13 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
 {
     using TS = TileShape<TZ>;
     __shared__ float v[TS::NV];
-    __shared__ __align__(16) uint8_t cb[TS::NC];
+    __shared__ __align__(16) uint8_t cb[TS::NC + 16]; // + a dummy slot for faces
     __shared__ uint64_t rowoff[TS::NROW];
     __shared__ uint32_t hist[256];
     __shared__ uint8_t cfg[kLevels][3];
     __shared__ QParams qp;
     __shared__ uint32_t skip;
+    __shared__ uint32_t red[8];
 
     const int t = threadIdx.x;
     hist[t] = 0;
@@ -327,32 +738,14 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
         const bool abs_mode = J.mode == 0;
         uint32_t kmn = 0xffffffffu, kmx = 0u;
         bool bad = false;
-        for (int i = t; i < TS::NROW * TS::EZ; i += blockDim.x) {
-            const int z = i % TS::EZ, r = i / TS::EZ;
-            const int y = r % kSide, x = r / kSide;
-            if (x < g.ex && y < g.ey && z < g.ez) {
-                const float val = J.field[rowoff[r] + z];
-                v[x * TS::PX + y * TS::PZ + z] = val;
-                if (abs_mode) {
-                    bad |= !isfinite(val);
-                    const uint32_t k = fkey(val);
-                    kmn = min(kmn, k);
-                    kmx = max(kmx, k);
-                }
-            }
-        }
+        const bool vec = (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.field) & 15) == 0;
+        load_tile_values<TZ>(v, J.field, rowoff, g, vec, abs_mode, kmn, kmx, bad);
         if (abs_mode) {
-            for (int o = 32; o > 0; o >>= 1) {
-                kmn = min(kmn, (uint32_t)__shfl_xor((int)kmn, o, 64));
-                kmx = max(kmx, (uint32_t)__shfl_xor((int)kmx, o, 64));
-            }
-            const int anybad = __any(bad);
-            if ((t & 63) == 0) {
-                atomicMin(&J.st->kmin, kmn);
-                atomicMax(&J.st->kmax, kmx);
-                if (anybad)
-                    atomicOr(&J.st->flags, (uint32_t)ST_NONFINITE);
-            }
+            if (__any(bad) && (t & 63) == 0)
+                atomicOr(&J.st->flags, (uint32_t)ST_NONFINITE);
+            block_minmax(kmn, kmx, red);
+            if (t == 0)
+                J.mm_part[u - J.tile_begin] = make_uint2(kmn, kmx);
         }
         // anchors owned by this tile: local (0, 0, 16j)
         if (t < TZ && 16 * t < g.ownz) {
@@ -365,17 +758,21 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
         __syncthreads();
         walk_levels<TZ, true>(v, cb, nullptr, g, cfg, qp);
         // codes of owned points -> global, histogram in LDS
-        if (g.ownz == TS::OZ && (dz & 3) == 0) {
-            for (int i = t; i < 16 * 16 * TS::OZ / 4; i += blockDim.x) {
-                const int w = i % (TS::OZ / 4), r = i / (TS::OZ / 4);
+        if (g.ownz == TS::OZ && (dz & 15) == 0) {
+            for (int i = t; i < 16 * 16 * TZ; i += blockDim.x) {
+                const int w = i % TZ, r = i / TZ;
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
-                    const uint32_t c4 = *reinterpret_cast<const uint32_t *>(&cb[r * TS::OZ + 4 * w]);
-                    *reinterpret_cast<uint32_t *>(J.codes + rowoff[x * kSide + y] + 4 * w) = c4;
-                    atomicAdd(&hist[c4 & 255], 1u);
-                    atomicAdd(&hist[(c4 >> 8) & 255], 1u);
-                    atomicAdd(&hist[(c4 >> 16) & 255], 1u);
-                    atomicAdd(&hist[c4 >> 24], 1u);
+                    const uint4 c16 = *reinterpret_cast<const uint4 *>(&cb[r * TS::OZ + 16 * w]);
+                    *reinterpret_cast<uint4 *>(J.codes + rowoff[x * kSide + y] + 16 * w) = c16;
+                    const uint32_t cw[4] = {c16.x, c16.y, c16.z, c16.w};
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        atomicAdd(&hist[cw[j] & 255], 1u);
+                        atomicAdd(&hist[(cw[j] >> 8) & 255], 1u);
+                        atomicAdd(&hist[(cw[j] >> 16) & 255], 1u);
+                        atomicAdd(&hist[cw[j] >> 24], 1u);
+                    }
                 }
             }
         } else {
@@ -473,31 +870,67 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
         }
         __syncthreads();
         const float *anchors = reinterpret_cast<const float *>(J.stream + J.off_anchors);
-        for (int i = t; i < TS::NROW * TS::EZ; i += blockDim.x) {
-            const int z = i % TS::EZ, r = i / TS::EZ;
-            const int y = r % kSide, x = r / kSide;
+        const bool vec = (dz & 15) == 0;
+        load_tile_codes<TZ>(cl, J.codes, rowoff, g, vec);
+        // anchors of the tile region: every coordinate a multiple of 16
+        if (t < 4 * (TZ + 1)) {
+            const int x = 16 * (t & 1), y = 16 * ((t >> 1) & 1), z = 16 * (t >> 2);
             if (x < g.ex && y < g.ey && z < g.ez) {
-                const int li = x * TS::PX + y * TS::PZ + z;
-                const uint64_t gi = rowoff[r] + z;
-                const uint8_t c = J.codes[gi];
-                cl[li] = c;
-                if ((x & 15) == 0 && (y & 15) == 0 && (z & 15) == 0) {
-                    const uint64_t ai = ((uint64_t)(bx + (x >> 4)) * J.nb[1] + (by + (y >> 4))) *
-                                            J.nb[2] +
-                                        bz0 + (z >> 4);
-                    v[li] = anchors[ai];
-                } else if (c == 0) {
-                    v[li] = J.out[gi]; // outlier value scattered beforehand
+                const uint64_t ai = ((uint64_t)(bx + (x >> 4)) * J.nb[1] + (by + (y >> 4))) *
+                                        J.nb[2] +
+                                    bz0 + (z >> 4);
+                v[x * TS::PX + y * TS::PZ + z] = anchors[ai];
+            }
+        }
+        __syncthreads();
+        // outliers (code 0, anchors excluded): exact values were scattered into
+        // the output beforehand; fetched in batches of 8 per thread
+        {
+            constexpr int NE = TS::NROW * TS::EZ;
+    #pragma nounroll
+        for (int i0 = 0; i0 < NE; i0 += 256 * 8) {
+                float ov[8];
+                bool hit[8];
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    const int i = i0 + t + 256 * k;
+                    const int z = i % TS::EZ, r = i / TS::EZ;
+                    const int y = r % kSide, x = r / kSide;
+                    hit[k] = i < NE && x < g.ex && y < g.ey && z < g.ez &&
+                             cl[x * TS::PX + y * TS::PZ + z] == 0 &&
+                             !((x & 15) == 0 && (y & 15) == 0 && (z & 15) == 0);
+                    ov[k] = hit[k] ? J.out[rowoff[r] + z] : 0.f;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    if (hit[k]) {
+                        const int i = i0 + t + 256 * k;
+                        const int z = i % TS::EZ, r = i / TS::EZ;
+                        const int y = r % kSide, x = r / kSide;
+                        v[x * TS::PX + y * TS::PZ + z] = ov[k];
+                    }
                 }
             }
         }
         __syncthreads();
         walk_levels<TZ, false>(v, nullptr, cl, g, cfg, qp);
-        for (int i = t; i < 16 * 16 * TS::OZ; i += blockDim.x) {
-            const int z = i % TS::OZ, r = i / TS::OZ;
-            const int y = r % 16, x = r / 16;
-            if (x < g.ownx && y < g.owny && z < g.ownz)
-                J.out[rowoff[x * kSide + y] + z] = v[x * TS::PX + y * TS::PZ + z];
+        if (g.ownz == TS::OZ && (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.out) & 15) == 0) {
+            for (int i = t; i < 16 * 16 * 4 * TZ; i += blockDim.x) {
+                const int w = i % (4 * TZ), r = i / (4 * TZ);
+                const int y = r % 16, x = r / 16;
+                if (x < g.ownx && y < g.owny) {
+                    const float *vp = v + x * TS::PX + y * TS::PZ + 4 * w;
+                    *reinterpret_cast<float4 *>(J.out + rowoff[x * kSide + y] + 4 * w) =
+                        make_float4(vp[0], vp[1], vp[2], vp[3]);
+                }
+            }
+        } else {
+            for (int i = t; i < 16 * 16 * TS::OZ; i += blockDim.x) {
+                const int z = i % TS::OZ, r = i / TS::OZ;
+                const int y = r % 16, x = r / 16;
+                if (x < g.ownx && y < g.owny && z < g.ownz)
+                    J.out[rowoff[x * kSide + y] + z] = v[x * TS::PX + y * TS::PZ + z];
+            }
         }
         __syncthreads();
     }

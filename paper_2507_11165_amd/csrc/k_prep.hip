@@ -20,8 +20,6 @@ __global__ __launch_bounds__(256) void k_init_compress(const Job *__restrict__ j
         if (t < kLevels * kCands)
             (&st->tune_err[0][0])[t] = 0;
         if (t == 0) {
-            st->kmin = 0xffffffffu;
-            st->kmax = 0u;
             st->flags = 0u;
             st->n_out = 0;
             st->payload_words = 0;
@@ -31,7 +29,7 @@ __global__ __launch_bounds__(256) void k_init_compress(const Job *__restrict__ j
         if (blockIdx.y == 0 && t < sizeof(Counters) / 4)
             reinterpret_cast<uint32_t *>(cnt)[t] = 0u;
     }
-    for (uint64_t i = blockIdx.x * 256ull + t; i < J.n_chunks; i += 256ull * gridDim.x) {
+    for (uint64_t i = blockIdx.x * 256ull + t; i < J.n_groups; i += 256ull * gridDim.x) {
         J.lb_a[i] = 0;
         J.lb_b[i] = 0;
     }
@@ -71,10 +69,12 @@ __device__ inline uint32_t wave_max_u32(uint32_t v)
 __global__ __launch_bounds__(256) void k_minmax(const Job *__restrict__ jobs, int njobs,
                                                 uint64_t total)
 {
+    __shared__ uint32_t red[8];
     const uint32_t t = threadIdx.x;
     for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
         const Job &J = jobs[find_job<WK_MM>(jobs, njobs, u)];
-        const uint64_t lo = (u - J.mm_begin) * kMmUnit;
+        const uint64_t lu = u - J.mm_begin;
+        const uint64_t lo = lu * kMmUnit;
         const uint64_t hi = min(lo + kMmUnit, J.N);
         const float *f = J.field;
         uint32_t kmn = 0xffffffffu, kmx = 0u;
@@ -103,15 +103,11 @@ __global__ __launch_bounds__(256) void k_minmax(const Job *__restrict__ jobs, in
                 kmx = max(kmx, key);
             }
         }
-        kmn = wave_min_u32(kmn);
-        kmx = wave_max_u32(kmx);
-        int anybad = __any(bad);
-        if ((t & 63) == 0) {
-            atomicMin(&J.st->kmin, kmn);
-            atomicMax(&J.st->kmax, kmx);
-            if (anybad)
-                atomicOr(&J.st->flags, (uint32_t)ST_NONFINITE);
-        }
+        if (__any(bad) && (t & 63) == 0)
+            atomicOr(&J.st->flags, (uint32_t)ST_NONFINITE);
+        block_minmax(kmn, kmx, red);
+        if (t == 0)
+            J.mm_part[lu] = make_uint2(kmn, kmx);
     }
 }
 
@@ -127,26 +123,32 @@ void launch_minmax(const Job *d_jobs, int njobs, uint64_t total, int grid, hipSt
 // Error bound: eps = eb (ABS) or eb * (max - min) (REL), formed in FP64 and
 // rounded down to FP32 so that it never exceeds the requested bound.
 // ---------------------------------------------------------------------------
-__global__ void k_eps(const Job *__restrict__ jobs, int njobs)
+__global__ __launch_bounds__(256) void k_eps(const Job *__restrict__ jobs, int njobs)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= njobs)
-        return;
-    const Job &J = jobs[j];
+    __shared__ uint32_t red[8];
+    const Job &J = jobs[blockIdx.x];
     FieldState *st = J.st;
     double e = J.eb;
     if (J.mode == 1) {
+        uint32_t kmn, kmx;
+        reduce_partials(J.mm_part, J.n_mm, kmn, kmx, red);
+        if (threadIdx.x != 0)
+            return;
+        st->kmin = kmn;
+        st->kmax = kmx;
         if (st->flags & ST_NONFINITE)
             return;
-        float vmin = fkey_inv(st->kmin), vmax = fkey_inv(st->kmax);
+        const float vmin = fkey_inv(kmn), vmax = fkey_inv(kmx);
         st->vmin = vmin;
         st->vmax = vmax;
-        double range = (double)vmax - (double)vmin;
+        const double range = (double)vmax - (double)vmin;
         if (range == 0.0) {
             st->flags |= ST_CONST;
             return;
         }
         e = J.eb * range;
+    } else if (threadIdx.x != 0) {
+        return;
     }
     float f = (float)e;
     if ((double)f > e)
@@ -159,7 +161,7 @@ __global__ void k_eps(const Job *__restrict__ jobs, int njobs)
 
 void launch_eps(const Job *d_jobs, int njobs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_eps, dim3((njobs + 63) / 64), dim3(64), 0, s, d_jobs, njobs);
+    hipLaunchKernelGGL(k_eps, dim3(njobs), dim3(256), 0, s, d_jobs, njobs);
 }
 
 // ---------------------------------------------------------------------------

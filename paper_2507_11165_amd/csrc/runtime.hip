@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -208,11 +209,25 @@ hiz_status ensure_pinned(hiz_ctx *c, uint64_t bytes)
     return HIZ_OK;
 }
 
+bool debug_on()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("HIZ_DEBUG");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
 int predict_grid(hiz_ctx *c, int tz, uint64_t total, bool rec)
 {
     int *cache = rec ? c->rec_bpc : c->pred_bpc;
-    if (!cache[tz])
+    if (!cache[tz]) {
         cache[tz] = rec ? reconstruct_blocks_per_cu(tz) : predict_blocks_per_cu(tz);
+        if (debug_on())
+            fprintf(stderr, "[hiz] %s tile_z=%d: %d CUs x %d workgroups per CU\n",
+                    rec ? "reconstruct" : "predict", tz, c->cus, cache[tz]);
+    }
     uint64_t g = (uint64_t)c->cus * cache[tz];
     if (g >= 8)
         g &= ~uint64_t(7);
@@ -504,8 +519,12 @@ hiz_status hiz_compress(hiz_ctx *c, const float *d_field, const uint64_t dims[3]
     const uint64_t o_st = A.take(sizeof(FieldState));
     const uint64_t o_cnt = A.take(sizeof(Counters));
     const uint64_t o_codes = A.take(N);
-    const uint64_t o_lba = A.take(8 * J.n_chunks);
-    const uint64_t o_lbb = A.take(8 * J.n_chunks);
+    J.n_groups = cdiv(J.n_chunks, kEncGroupChunks);
+    const uint64_t o_lba = A.take(8 * J.n_groups);
+    const uint64_t o_lbb = A.take(8 * J.n_groups);
+    const uint64_t o_woff = A.take(8 * J.n_chunks);
+    const uint64_t o_zoff = A.take(8 * J.n_chunks);
+    const uint64_t o_mm = A.take(8 * std::max<uint64_t>(J.n_mm, J.n_tiles));
     hiz_status rc = ensure_ws(c, A.off);
     if (rc)
         return rc;
@@ -517,6 +536,9 @@ hiz_status hiz_compress(hiz_ctx *c, const float *d_field, const uint64_t dims[3]
     J.codes = ws + o_codes;
     J.lb_a = reinterpret_cast<uint64_t *>(ws + o_lba);
     J.lb_b = reinterpret_cast<uint64_t *>(ws + o_lbb);
+    J.mm_part = reinterpret_cast<uint2 *>(ws + o_mm);
+    J.woff = reinterpret_cast<uint64_t *>(ws + o_woff);
+    J.zoff = reinterpret_cast<uint64_t *>(ws + o_zoff);
     Job *d_job = reinterpret_cast<Job *>(ws + o_job);
     Counters *d_cnt = reinterpret_cast<Counters *>(ws + o_cnt);
     memcpy(c->pinned, &J, sizeof(J));
@@ -525,7 +547,7 @@ hiz_status hiz_compress(hiz_ctx *c, const float *d_field, const uint64_t dims[3]
     HIP_TRY(c, hipMemcpyAsync(d_job, c->pinned, sizeof(Job), hipMemcpyHostToDevice, s));
     {
         Scope sc(c, s, "init");
-        launch_init_compress(d_job, 1, J.n_chunks, d_cnt, s);
+        launch_init_compress(d_job, 1, J.n_groups, d_cnt, s);
     }
     if (J.n_mm) {
         Scope sc(c, s, "minmax");
@@ -552,10 +574,14 @@ hiz_status hiz_compress(hiz_ctx *c, const float *d_field, const uint64_t dims[3]
         launch_codebook(d_job, 1, s);
     }
     {
-        if (!c->enc_bpc)
+        if (!c->enc_bpc) {
             c->enc_bpc = encode_blocks_per_cu();
+            if (debug_on())
+                fprintf(stderr, "[hiz] encode: %d CUs x %d workgroups per CU\n", c->cus,
+                        c->enc_bpc);
+        }
         Scope sc(c, s, "encode");
-        launch_encode(d_job, 1, J.n_chunks, d_cnt, c->cus * c->enc_bpc, s);
+        launch_encode(d_job, 1, J.n_chunks, J.n_groups, d_cnt, c->cus * c->enc_bpc, s);
     }
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipMemcpyAsync(h_res, J.st, kResultBytes, hipMemcpyDeviceToHost, s));
