@@ -126,6 +126,65 @@ hiz_status hiz_decompress(hiz_ctx *ctx, const void *d_in, uint64_t in_size,
  * HIZ_ERR_ARG. */
 hiz_status hiz_inspect(const void *h_stream, uint64_t n, hiz_info *out);
 
+/* ---- Batches: many independent fields per call -------------------------
+ * A batch of n fields of any shapes runs each stage of the method as ONE
+ * launch over the concatenated work of all fields (range and bound, tuner,
+ * interpolation + quantization + histogram, codebook, encoding; or decoding,
+ * outliers, reconstruction). Every field keeps its own bound, tuned level
+ * configuration, histogram, codebook and chunk table, so each output stream
+ * is byte-identical to what hiz_compress / hiz_decompress give for that
+ * field alone. n may be 0; at most 4096.
+ *
+ * Arrays are host arrays of n entries (dims: 3n values, field i's dims at
+ * dims[3i..3i+2]); params, when not NULL, apply to every field and their
+ * tile_z is shared. Per-field failures are reported in statuses[i] (may be
+ * NULL) and do not stop the other fields; the call returns HIZ_OK when every
+ * field succeeded, else the first failing field's status, with a message
+ * naming the field. A failure of the call itself (bad n, NULL arrays, no
+ * memory, HIP error) returns before any field is processed.
+ *
+ * The *_submit forms only enqueue the work on `stream` and return; the batch
+ * is then pending on the context until hiz_batch_finish (which waits for it)
+ * and the context accepts no other call that launches work meanwhile
+ * (HIZ_ERR_ARG). Decompression submit reads the stream headers first, so it
+ * synchronizes `stream` once before enqueueing. Input and output buffers must
+ * stay valid until hiz_batch_finish returns. */
+hiz_status hiz_compress_batch(hiz_ctx *ctx, int n, const float *const *d_fields,
+                              const uint64_t *dims, const int *modes, const double *ebs,
+                              const hiz_params *params, void *const *d_outs,
+                              const uint64_t *out_caps, uint64_t *out_sizes,
+                              hiz_status *statuses, hiz_stream_t stream);
+/* dims_out (3n values, may be NULL) receives each field's dims. */
+hiz_status hiz_decompress_batch(hiz_ctx *ctx, int n, const void *const *d_ins,
+                                const uint64_t *in_sizes, float *const *d_fields,
+                                const uint64_t *field_caps, uint64_t *dims_out,
+                                hiz_status *statuses, hiz_stream_t stream);
+hiz_status hiz_compress_batch_submit(hiz_ctx *ctx, int n, const float *const *d_fields,
+                                     const uint64_t *dims, const int *modes, const double *ebs,
+                                     const hiz_params *params, void *const *d_outs,
+                                     const uint64_t *out_caps, hiz_stream_t stream);
+hiz_status hiz_decompress_batch_submit(hiz_ctx *ctx, int n, const void *const *d_ins,
+                                       const uint64_t *in_sizes, float *const *d_fields,
+                                       const uint64_t *field_caps, hiz_stream_t stream);
+/* 1 when no batch is pending or the pending one has completed on the device
+ * (never blocks), else 0. */
+int hiz_batch_ready(hiz_ctx *ctx);
+/* Wait for the pending batch. sizes[i] (may be NULL): stream bytes of field i
+ * (compression; the size needed on HIZ_ERR_BUFSZ) or elements written
+ * (decompression). dims (3n, may be NULL): decompressed dims. */
+hiz_status hiz_batch_finish(hiz_ctx *ctx, uint64_t *sizes, uint64_t *dims,
+                            hiz_status *statuses);
+
+/* HIP-graph replay. When on, each call's launch sequence (Job-table upload,
+ * every kernel, result download) is captured once per launch geometry into a
+ * HIP graph and replayed by one hipGraphLaunch; calls with the same geometry
+ * (field count, shapes, chunk lengths, tuner samples, outlier count for
+ * decompression) reuse it. Up to 8 graphs are kept per context. Outputs do
+ * not depend on this switch. Fails with HIZ_ERR_ARG while a batch is pending. */
+hiz_status hiz_set_graphs(hiz_ctx *ctx, int on);
+/* Graphs built and replays launched on this context so far. */
+void hiz_graph_stats(const hiz_ctx *ctx, uint64_t *builds, uint64_t *replays);
+
 /* Per-kernel timing of the calls made on this context while profiling is on
  * (HIP events recorded on the caller's stream around each launch). */
 typedef struct {

@@ -149,6 +149,7 @@ void launch_encode(const Job *d_jobs, int njobs, uint64_t total_chunks, uint64_t
 int encode_blocks_per_cu();
 
 void launch_fill(float *out, uint64_t n, float v, hipStream_t s);
+void launch_gather_results(const Job *d_jobs, int njobs, void *d_dst, hipStream_t s);
 void launch_init_decompress(const Job *d_jobs, int njobs, uint64_t max_blocks, Counters *cnt,
                             hipStream_t s);
 void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s);

@@ -200,7 +200,7 @@ __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restri
     constexpr int stB = B == 0 ? TS::PX : TS::PZ;
     constexpr int stC = C == 1 ? TS::PZ : 1;
     constexpr int M = (1 << A) | (MB << B) | (MC << C);
-    const int K = 8 / S;
+    const int K = 8 >> __builtin_ctz(S);
     const int last = nA - 1;
     const int li0 = x0 * TS::PX + y0 * TS::PZ + z0;
     // block bounds of the cross axes
@@ -277,28 +277,41 @@ __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restri
 
 enum : int { M_EVEN = 0, M_ODD = 1, M_ALL = 2 };
 
-__device__ __forceinline__ int mode_count(int mode, int n, int S)
+// Coordinates of a mode in [0, n - 1] at stride S = 2^ls (shifts, no division).
+__device__ __forceinline__ int mode_count(int mode, int n, int ls)
 {
     if (mode == M_EVEN)
-        return (n - 1) / (2 * S) + 1;
+        return ((n - 1) >> (ls + 1)) + 1;
     if (mode == M_ODD)
-        return n - 1 >= S ? (n - 1 - S) / (2 * S) + 1 : 0;
-    return (n - 1) / S + 1;
+        return n - 1 >= (1 << ls) ? ((n - 1 - (1 << ls)) >> (ls + 1)) + 1 : 0;
+    return ((n - 1) >> ls) + 1;
 }
 __device__ __forceinline__ int mode_coord(int mode, int i, int S)
 {
     return mode == M_EVEN ? 2 * i * S : (mode == M_ODD ? (2 * i + 1) * S : i * S);
 }
 
-// quotient n / d for n, d < 2^16 with a multiply (m = ceil(2^32 / d))
+// quotient n / d for n, d < 2^16 with a multiply (m = floor((2^32 - 1) / d) + 1)
 __device__ __forceinline__ uint32_t qdiv(uint32_t n, uint32_t d, uint32_t m)
 {
     return d == 1 ? n : __umulhi(n, m);
 }
-__device__ __forceinline__ uint32_t qmagic(uint32_t d)
+// The multipliers of every divisor a line group can have (line counts per
+// cross axis up to 17 and 16 * 4 + 1, and their products), built at compile
+// time so that no division runs on the device.
+constexpr int kMagicMax = kSide * (16 * 4 + 1);
+struct MagicTable {
+    uint32_t m[kMagicMax + 1];
+};
+constexpr MagicTable make_magic_table()
 {
-    return d <= 1 ? 0u : (uint32_t)(0xffffffffu / d + 1u);
+    MagicTable t{};
+    for (int d = 0; d <= kMagicMax; d++)
+        t.m[d] = d <= 1 ? 0u : (uint32_t)(0xffffffffu / (uint32_t)d + 1u);
+    return t;
 }
+__constant__ MagicTable c_magic = make_magic_table();
+__device__ __forceinline__ uint32_t qmagic(uint32_t d) { return c_magic.m[d]; }
 
 // A group of lines of one kind: axis A plus which cross axes are odd and
 // interpolated (MD), with the coordinate modes of the two cross axes.
@@ -310,7 +323,7 @@ struct LineGroup {
 };
 
 __device__ __forceinline__ LineGroup make_group(int kind, int A, int modeB, int modeC, int S,
-                                                const Geo &g, int TZ)
+                                                int ls, const Geo &g, int TZ)
 {
     LineGroup G;
     G.kind = kind;
@@ -319,10 +332,10 @@ __device__ __forceinline__ LineGroup make_group(int kind, int A, int modeB, int 
     G.modeC = modeC;
     const int nB = A == 0 ? g.ey : g.ex;
     const int nC = A == 2 ? g.ey : g.ez;
-    G.cntB = mode_count(modeB, nB, S);
-    G.cntC = mode_count(modeC, nC, S);
+    G.cntB = mode_count(modeB, nB, ls);
+    G.cntC = mode_count(modeC, nC, ls);
     if (A == 2)
-        G.ncell = g.ez - 1 >= S ? min(TZ, (g.ez - 1 - S) / 16 + 1) : 0;
+        G.ncell = g.ez - 1 >= S ? min(TZ, ((g.ez - 1 - S) >> 4) + 1) : 0;
     else
         G.ncell = 1;
     if ((A == 0 && g.ex - 1 < S) || (A == 1 && g.ey - 1 < S))
@@ -375,22 +388,23 @@ template <int TZ, bool CUB, bool COMP, bool FULL>
 __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g,
                                             int S, bool md, int perm, const QParams &q)
 {
+    const int ls = __builtin_ctz(S);
     for (int sub = 1; sub <= 3; sub++) {
         LineGroup G0, G1, G2;
         int ng;
         if (md) {
             if (sub == 1) {
-                G0 = make_group(0, 2, M_EVEN, M_EVEN, S, g, TZ);
-                G1 = make_group(1, 1, M_EVEN, M_EVEN, S, g, TZ);
-                G2 = make_group(2, 0, M_EVEN, M_EVEN, S, g, TZ);
+                G0 = make_group(0, 2, M_EVEN, M_EVEN, S, ls, g, TZ);
+                G1 = make_group(1, 1, M_EVEN, M_EVEN, S, ls, g, TZ);
+                G2 = make_group(2, 0, M_EVEN, M_EVEN, S, ls, g, TZ);
                 ng = 3;
             } else if (sub == 2) {
-                G0 = make_group(3, 0, M_ODD, M_EVEN, S, g, TZ);
-                G1 = make_group(4, 2, M_ODD, M_EVEN, S, g, TZ);
-                G2 = make_group(5, 2, M_EVEN, M_ODD, S, g, TZ);
+                G0 = make_group(3, 0, M_ODD, M_EVEN, S, ls, g, TZ);
+                G1 = make_group(4, 2, M_ODD, M_EVEN, S, ls, g, TZ);
+                G2 = make_group(5, 2, M_EVEN, M_ODD, S, ls, g, TZ);
                 ng = 3;
             } else {
-                G0 = make_group(6, 2, M_ODD, M_ODD, S, g, TZ);
+                G0 = make_group(6, 2, M_ODD, M_ODD, S, ls, g, TZ);
                 G1 = G0;
                 G2 = G0;
                 ng = 1;
@@ -406,7 +420,7 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
             }
             const int modeB = earlyB ? M_ALL : M_EVEN;
             const int modeC = earlyC ? M_ALL : M_EVEN;
-            G0 = make_group(A == 2 ? 0 : (A == 1 ? 1 : 2), A, modeB, modeC, S, g, TZ);
+            G0 = make_group(A == 2 ? 0 : (A == 1 ? 1 : 2), A, modeB, modeC, S, ls, g, TZ);
             G1 = G0;
             G2 = G0;
             ng = 1;

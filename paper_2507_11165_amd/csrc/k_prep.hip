@@ -426,4 +426,25 @@ void launch_fill(float *out, uint64_t n, float v, hipStream_t s)
     hipLaunchKernelGGL(k_fill, dim3((uint32_t)g), dim3(256), 0, s, out, n, v);
 }
 
+// ---------------------------------------------------------------------------
+// The first bytes of every job's state, packed for one device-to-host copy.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather_results(const Job *__restrict__ jobs, int njobs,
+                                                        uint32_t *__restrict__ dst)
+{
+    constexpr int W = kResultBytes / 4;
+    const uint64_t i = blockIdx.x * 256ull + threadIdx.x;
+    if (i >= (uint64_t)njobs * W)
+        return;
+    const int j = (int)(i / W), w = (int)(i % W);
+    dst[i] = reinterpret_cast<const uint32_t *>(jobs[j].st)[w];
+}
+
+void launch_gather_results(const Job *d_jobs, int njobs, void *d_dst, hipStream_t s)
+{
+    const uint64_t n = (uint64_t)njobs * (kResultBytes / 4);
+    hipLaunchKernelGGL(k_gather_results, dim3((uint32_t)cdiv(n, 256)), dim3(256), 0, s, d_jobs,
+                       njobs, static_cast<uint32_t *>(d_dst));
+}
+
 } // namespace hiz

@@ -1,6 +1,12 @@
 // Host runtime of the hiz library: context and device workspace, job
-// descriptors, the launch sequence of compression and decompression, stream
-// header parsing, per-kernel profiling, and the C ABI declared in hiz.h.
+// descriptors, the launch sequence of (batched) compression and
+// decompression, HIP-graph replay of that sequence, stream header parsing,
+// per-kernel profiling, and the C ABI declared in hiz.h.
+//
+// Every call, single or batched, builds one Job per field and runs each stage
+// of the method as ONE launch over the concatenated work units of all its
+// fields (work-list prefixes in the Job table), so a batch of many uneven
+// fields costs the same number of launches as a single field.
 #include "hiz.h"
 #include "hiz_internal.h"
 
@@ -18,6 +24,8 @@ using namespace hiz;
 namespace {
 
 constexpr uint64_t kMaxN = 1ull << 40;
+constexpr int kMaxBatch = 4096;  // fields per batched call
+constexpr int kGraphSlots = 8;   // instantiated graphs kept per context
 
 struct KStat {
     std::string name;
@@ -28,6 +36,41 @@ struct KStat {
 struct Pending {
     int stat;
     hipEvent_t a, b;
+};
+
+// Launch geometry of one enqueued sequence: equal keys replay the same graph
+// (the Job table itself is re-uploaded by the graph's first node).
+struct GraphKey {
+    int kind; // 0 compress, 1 decompress
+    int njobs;
+    int tz;
+    int pad;
+    uint64_t v[12];
+    const void *ws;
+    const void *pinned;
+};
+
+struct GraphSlot {
+    GraphKey key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+};
+
+// The batch most recently enqueued on a context, until hiz_batch_finish.
+struct Batch {
+    bool pending = false;
+    int kind = 0;                      // 0 compress, 1 decompress
+    int n = 0;                         // caller fields
+    int njobs = 0;                     // fields with device work
+    std::vector<int> field;            // job -> caller field
+    std::vector<hiz_status> status;    // caller field -> status known before launch
+    std::vector<uint64_t> size;        // caller field -> bytes (compress) / elements (decompress)
+    std::vector<uint64_t> cap;         // caller field -> output capacity
+    std::vector<uint64_t> dims;        // caller field -> dims parsed from the header (decompress)
+    std::vector<uint64_t> n_out;       // job -> outliers named by the header (decompress)
+    std::vector<std::string> msg;      // caller field -> message of a failure before launch
+    hipStream_t s = nullptr;
+    uint8_t *h_res = nullptr;          // pinned: njobs x kResultBytes
 };
 
 } // namespace
@@ -48,6 +91,13 @@ struct hiz_ctx {
     int pred_bpc[5] = {0, 0, 0, 0, 0};
     int rec_bpc[5] = {0, 0, 0, 0, 0};
     int enc_bpc = 0;
+    bool graphs = false;
+    hipStream_t cap_stream = nullptr;
+    GraphSlot gslot[kGraphSlots];
+    uint64_t gclock = 0;
+    uint64_t graph_builds = 0, graph_replays = 0;
+    hipEvent_t done = nullptr;
+    Batch batch;
 };
 
 namespace {
@@ -62,6 +112,16 @@ hiz_status fail(hiz_ctx *c, hiz_status st, const char *fmt, ...)
     if (c)
         c->err = buf;
     return st;
+}
+
+std::string fmt_msg(const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    return buf;
 }
 
 #define HIP_TRY(ctx, expr)                                                                        \
@@ -120,12 +180,15 @@ int stat_index(hiz_ctx *c, const char *name)
     return (int)c->stats.size() - 1;
 }
 
+// HIP events around one launch on the launch stream; off while a graph is
+// being captured (events would become graph nodes).
 struct Scope {
     hiz_ctx *c;
     hipStream_t s;
     Pending p;
     bool on;
-    Scope(hiz_ctx *c_, hipStream_t s_, const char *name) : c(c_), s(s_), on(c_->profiling)
+    Scope(hiz_ctx *c_, hipStream_t s_, const char *name, bool allow = true)
+        : c(c_), s(s_), on(c_->profiling && allow)
     {
         if (on) {
             p.stat = stat_index(c, name);
@@ -158,6 +221,17 @@ void collect_profile(hiz_ctx *c)
     c->next_event = 0;
 }
 
+// ---- graphs ----
+void drop_graphs(hiz_ctx *c)
+{
+    for (GraphSlot &g : c->gslot) {
+        if (g.exec)
+            hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.used = 0;
+    }
+}
+
 // ---- workspace ----
 struct Arena {
     uint64_t off = 0;
@@ -175,6 +249,7 @@ hiz_status ensure_ws(hiz_ctx *c, uint64_t bytes)
         return HIZ_OK;
     if (c->ws) {
         hipDeviceSynchronize();
+        drop_graphs(c);
         hipFree(c->ws);
         c->ws = nullptr;
         c->ws_size = 0;
@@ -194,11 +269,14 @@ hiz_status ensure_pinned(hiz_ctx *c, uint64_t bytes)
 {
     if (bytes <= c->pinned_size)
         return HIZ_OK;
-    if (c->pinned)
+    if (c->pinned) {
+        hipDeviceSynchronize();
+        drop_graphs(c);
         hipHostFree(c->pinned);
+    }
     c->pinned = nullptr;
     c->pinned_size = 0;
-    uint64_t want = std::max<uint64_t>(bytes, 64 * 1024);
+    uint64_t want = std::max<uint64_t>(bytes + bytes / 4, 64 * 1024);
     if (hipHostMalloc((void **)&c->pinned, want, hipHostMallocDefault) != hipSuccess) {
         c->pinned = nullptr;
         hipGetLastError();
@@ -236,6 +314,16 @@ int predict_grid(hiz_ctx *c, int tz, uint64_t total, bool rec)
     return (int)std::max<uint64_t>(1, g);
 }
 
+int encode_grid(hiz_ctx *c)
+{
+    if (!c->enc_bpc) {
+        c->enc_bpc = encode_blocks_per_cu();
+        if (debug_on())
+            fprintf(stderr, "[hiz] encode: %d CUs x %d workgroups per CU\n", c->cus, c->enc_bpc);
+    }
+    return c->cus * c->enc_bpc;
+}
+
 // ---- header parsing (host) ----
 template <typename T> T get_le(const uint8_t *p)
 {
@@ -252,25 +340,33 @@ struct Parsed {
     float const_value;
 };
 
-hiz_status parse_header(hiz_ctx *c, const uint8_t *h, uint64_t n, uint64_t in_size, Parsed *P)
+// Checks a stream header; `msg` receives the reason of a failure.
+hiz_status parse_header(std::string *msg, const uint8_t *h, uint64_t n, uint64_t in_size,
+                        Parsed *P)
 {
+#define BAD(text)                                                                                 \
+    do {                                                                                          \
+        if (msg)                                                                                  \
+            *msg = text;                                                                          \
+        return HIZ_ERR_CORRUPT;                                                                   \
+    } while (0)
     memset(P, 0, sizeof(*P));
     hiz_info &I = P->info;
     if (n < (uint64_t)kHdrBytes || in_size < (uint64_t)kHdrBytes)
-        return fail(c, HIZ_ERR_CORRUPT, "stream shorter than its header");
+        BAD("stream shorter than its header");
     if (get_le<uint32_t>(h + H_MAGIC) != kMagic || get_le<uint16_t>(h + H_VERSION) != kVersion)
-        return fail(c, HIZ_ERR_CORRUPT, "bad magic or version");
+        BAD("bad magic or version");
     I.mode = h[H_MODE];
     const uint8_t flags = h[H_FLAGS];
     if (I.mode > 1 || (flags & ~3))
-        return fail(c, HIZ_ERR_CORRUPT, "bad mode or flags");
+        BAD("bad mode or flags");
     uint64_t N = 1;
     for (int k = 0; k < 3; k++) {
         I.dims[k] = get_le<uint64_t>(h + H_DIMS + 8 * k);
         if (I.dims[k] == 0 || I.dims[k] > kMaxN)
-            return fail(c, HIZ_ERR_CORRUPT, "bad dims");
+            BAD("bad dims");
         if (N > kMaxN / I.dims[k])
-            return fail(c, HIZ_ERR_CORRUPT, "field too large");
+            BAD("field too large");
         N *= I.dims[k];
     }
     P->N = N;
@@ -282,41 +378,41 @@ hiz_status parse_header(hiz_ctx *c, const uint8_t *h, uint64_t n, uint64_t in_si
     if (flags & kFlagConst) {
         I.constant = 1;
         if (I.total_bytes != kHdrBytes + 4u || in_size < I.total_bytes)
-            return fail(c, HIZ_ERR_CORRUPT, "bad constant stream");
+            BAD("bad constant stream");
         if (n >= kHdrBytes + 4u)
             P->const_value = get_le<float>(h + kHdrBytes);
         return HIZ_OK;
     }
     if (h[H_ASTRIDE] != kAnchor || h[H_NLEV] != kLevels)
-        return fail(c, HIZ_ERR_CORRUPT, "bad anchor stride or level count");
+        BAD("bad anchor stride or level count");
     for (int l = 0; l < kLevels; l++) {
         for (int k = 0; k < 3; k++)
             I.level_cfg[l][k] = h[H_CFG + 3 * l + k];
         if (I.level_cfg[l][0] > 1 || I.level_cfg[l][1] > 1 || I.level_cfg[l][2] > 5)
-            return fail(c, HIZ_ERR_CORRUPT, "bad level configuration");
+            BAD("bad level configuration");
     }
     I.chunk = get_le<uint32_t>(h + H_CHUNK);
     if (I.chunk < 256 || I.chunk > 65536 || (I.chunk & (I.chunk - 1)))
-        return fail(c, HIZ_ERR_CORRUPT, "bad chunk length");
+        BAD("bad chunk length");
     I.n_outliers = get_le<uint64_t>(h + H_NOUT);
     I.payload_words = get_le<uint64_t>(h + H_PWORDS);
     I.n_chunks = get_le<uint64_t>(h + H_NCHUNKS);
     const uint64_t n_anchors = get_le<uint64_t>(h + H_NANCH);
     P->idx_bytes = N < (1ull << 32) ? 4 : 8;
     if (((flags & kFlagIdx64) != 0) != (P->idx_bytes == 8))
-        return fail(c, HIZ_ERR_CORRUPT, "bad index width flag");
+        BAD("bad index width flag");
     if (I.n_chunks != cdiv(N, I.chunk))
-        return fail(c, HIZ_ERR_CORRUPT, "bad chunk count");
+        BAD("bad chunk count");
     if (n_anchors != cdiv(I.dims[0], kAnchor) * cdiv(I.dims[1], kAnchor) * cdiv(I.dims[2], kAnchor))
-        return fail(c, HIZ_ERR_CORRUPT, "bad anchor count");
+        BAD("bad anchor count");
     if (I.n_outliers > N || I.payload_words > N + I.n_chunks)
-        return fail(c, HIZ_ERR_CORRUPT, "bad outlier or payload size");
+        BAD("bad outlier or payload size");
     P->off_anchors = align16(kOffChunks + 4 * I.n_chunks);
     P->off_oidx = align16(P->off_anchors + 4 * n_anchors);
     P->off_oval = align16(P->off_oidx + (uint64_t)P->idx_bytes * I.n_outliers);
     P->off_payload = align16(P->off_oval + 4 * I.n_outliers);
     if (I.total_bytes != P->off_payload + 4 * I.payload_words || I.total_bytes > in_size)
-        return fail(c, HIZ_ERR_CORRUPT, "stream size does not match its header");
+        BAD("stream size does not match its header");
     if (n >= (uint64_t)kOffChunks) {
         // the code lengths must form a complete prefix code (one symbol: length 1)
         const uint8_t *len = h + kOffLen;
@@ -326,14 +422,15 @@ hiz_status parse_header(hiz_ctx *c, const uint8_t *h, uint64_t n, uint64_t in_si
             if (!len[i])
                 continue;
             if (len[i] > kMaxCodeLen)
-                return fail(c, HIZ_ERR_CORRUPT, "code length above 32");
+                BAD("code length above 32");
             kraft += 1ull << (32 - len[i]);
             nsym++;
         }
         if (nsym == 0 || (nsym == 1 && kraft != (1ull << 31)) || (nsym > 1 && kraft != (1ull << 32)))
-            return fail(c, HIZ_ERR_CORRUPT, "code lengths do not form a complete prefix code");
+            BAD("code lengths do not form a complete prefix code");
     }
     return HIZ_OK;
+#undef BAD
 }
 
 bool valid_cfg(const uint8_t cfg[4][3])
@@ -342,6 +439,600 @@ bool valid_cfg(const uint8_t cfg[4][3])
         if (cfg[l][0] > 1 || cfg[l][1] > 1 || cfg[l][2] > 5)
             return false;
     return true;
+}
+
+// Shared parameters of a call (NULL = defaults) and its tile shape.
+hiz_status resolve_params(hiz_ctx *c, const hiz_params *params, hiz_params &p, int &tz)
+{
+    memset(&p, 0, sizeof(p));
+    p.tune = 1;
+    for (int l = 0; l < 4; l++)
+        p.level_cfg[l][0] = HIZ_SPLINE_CUBIC;
+    if (params)
+        p = *params;
+    if (!valid_cfg(p.level_cfg))
+        return fail(c, HIZ_ERR_ARG, "bad level configuration");
+    if (p.chunk && (p.chunk < 256 || p.chunk > 65536 || (p.chunk & (p.chunk - 1))))
+        return fail(c, HIZ_ERR_ARG, "chunk must be a power of two in [256, 65536]");
+    tz = p.tile_z ? (int)p.tile_z : kDefaultTileZ;
+    if (tz != 1 && tz != 2 && tz != 4)
+        return fail(c, HIZ_ERR_ARG, "tile_z must be 1, 2 or 4");
+    return HIZ_OK;
+}
+
+// Geometry and parameters of one field to compress; device pointers are
+// filled in by the caller once the workspace is laid out.
+hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode, double eb,
+                         const hiz_params &p, int tz, void *d_out, uint64_t out_cap, Job &J,
+                         std::string &msg)
+{
+    if (!d_field || !dims || !d_out) {
+        msg = "NULL argument";
+        return HIZ_ERR_ARG;
+    }
+    if (mode != HIZ_ABS && mode != HIZ_REL) {
+        msg = "bad error-bound mode";
+        return HIZ_ERR_ARG;
+    }
+    if (!(eb > 0.0) || !std::isfinite(eb)) {
+        msg = "error bound must be finite and positive";
+        return HIZ_ERR_ARG;
+    }
+    if ((reinterpret_cast<uintptr_t>(d_field) & 3) || (reinterpret_cast<uintptr_t>(d_out) & 15)) {
+        msg = "field must be 4-byte and stream 16-byte aligned";
+        return HIZ_ERR_ARG;
+    }
+    uint64_t N = 1;
+    for (int k = 0; k < 3; k++) {
+        if (dims[k] == 0 || dims[k] > kMaxN || N > kMaxN / dims[k]) {
+            msg = "bad dims";
+            return HIZ_ERR_ARG;
+        }
+        N *= dims[k];
+    }
+    const uint32_t chunk = p.chunk ? p.chunk : default_chunk(N);
+    memset(&J, 0, sizeof(J));
+    J.field = d_field;
+    J.stream = static_cast<uint8_t *>(d_out);
+    J.cap = out_cap;
+    for (int k = 0; k < 3; k++) {
+        J.dims[k] = dims[k];
+        J.nb[k] = (uint32_t)cdiv(dims[k], kAnchor);
+        J.n_full[k] = dims[k] >= (uint64_t)kSide ? (uint32_t)((dims[k] - kSide) / kAnchor + 1) : 0;
+    }
+    J.N = N;
+    J.ntz = (uint32_t)cdiv(J.nb[2], tz);
+    J.n_anchors = (uint64_t)J.nb[0] * J.nb[1] * J.nb[2];
+    J.chunk = chunk;
+    J.log2_chunk = (uint32_t)ilog2(chunk);
+    J.n_chunks = cdiv(N, chunk);
+    J.off_anchors = align16(kOffChunks + 4 * J.n_chunks);
+    J.mode = mode;
+    J.tune = p.tune ? 1 : 0;
+    J.eb = eb;
+    memcpy(J.cfg_forced, p.level_cfg, sizeof(J.cfg_forced));
+    J.idx_bytes = N < (1ull << 32) ? 4 : 8;
+    J.n_mm = mode == HIZ_REL ? cdiv(N, 16384) : 0;
+    const uint64_t n_full = (uint64_t)J.n_full[0] * J.n_full[1] * J.n_full[2];
+    if (J.tune && n_full > 0) {
+        // Sec. 5.1.3: about 0.2 % of the points, in whole full blocks
+        uint64_t ns = std::max<uint64_t>(1, cdiv(2 * N, 1000ull * 4913ull));
+        J.n_samples = (uint32_t)std::min<uint64_t>(ns, n_full);
+    }
+    J.n_tune = (uint64_t)J.n_samples * 9;
+    J.n_tiles = (uint64_t)J.nb[0] * J.nb[1] * J.ntz;
+    J.n_groups = cdiv(J.n_chunks, kEncGroupChunks);
+    return HIZ_OK;
+}
+
+// Geometry of one field to decompress from its parsed header.
+void plan_decompress(const Parsed &P, const void *d_in, uint64_t in_size, float *d_field, int tz,
+                     Job &J)
+{
+    memset(&J, 0, sizeof(J));
+    J.out = d_field;
+    J.stream = const_cast<uint8_t *>(static_cast<const uint8_t *>(d_in));
+    J.cap = in_size;
+    for (int k = 0; k < 3; k++) {
+        J.dims[k] = P.info.dims[k];
+        J.nb[k] = (uint32_t)cdiv(J.dims[k], kAnchor);
+    }
+    J.N = P.N;
+    J.ntz = (uint32_t)cdiv(J.nb[2], tz);
+    J.n_anchors = (uint64_t)J.nb[0] * J.nb[1] * J.nb[2];
+    J.chunk = P.info.chunk;
+    J.log2_chunk = (uint32_t)ilog2(J.chunk);
+    J.n_chunks = P.info.n_chunks;
+    J.off_anchors = P.off_anchors;
+    J.mode = P.info.mode;
+    J.eb = P.info.eb;
+    memcpy(J.cfg_forced, P.info.level_cfg, sizeof(J.cfg_forced));
+    J.idx_bytes = (uint8_t)P.idx_bytes;
+    J.n_tiles = (uint64_t)J.nb[0] * J.nb[1] * J.ntz;
+    J.n_dblk = cdiv(J.n_chunks, 256);
+    J.off_oidx = P.off_oidx;
+    J.off_oval = P.off_oval;
+    J.off_payload = P.off_payload;
+    J.n_out = P.info.n_outliers;
+    J.payload_words = P.info.payload_words;
+    J.eps = P.info.eps;
+}
+
+// Totals of one enqueued sequence (also the graph key's payload).
+struct Totals {
+    uint64_t mm = 0, tune = 0, tiles = 0, chunks = 0, groups = 0, dblk = 0, out = 0;
+    uint64_t max_groups = 0, max_dblk = 0;
+};
+
+// Lay out the workspace for `jobs`, set their prefixes and device pointers,
+// and stage the Job table in pinned memory. Returns the device addresses of
+// the Job table, the counters and the result block.
+struct Layout {
+    Job *d_jobs;
+    Counters *d_cnt;
+    uint8_t *d_res;
+    uint8_t *h_res;
+};
+
+hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, Totals &T, Layout &L)
+{
+    const int nj = (int)jobs.size();
+    Arena A;
+    const uint64_t o_jobs = A.take(sizeof(Job) * nj);
+    const uint64_t o_cnt = A.take(sizeof(Counters));
+    const uint64_t o_res = A.take((uint64_t)kResultBytes * nj);
+    std::vector<uint64_t> o_st(nj), o_dt(nj), o_codes(nj), o_lba(nj), o_lbb(nj), o_woff(nj),
+        o_zoff(nj), o_mm(nj);
+    T = Totals();
+    for (int j = 0; j < nj; j++) {
+        Job &J = jobs[j];
+        o_st[j] = A.take(sizeof(FieldState));
+        o_codes[j] = A.take(J.N);
+        if (decompress) {
+            o_dt[j] = A.take(sizeof(DecTables));
+            o_lba[j] = A.take(8 * J.n_dblk);
+            J.tile_begin = T.tiles;
+            J.dblk_begin = T.dblk;
+            J.out_begin = T.out;
+            T.tiles += J.n_tiles;
+            T.dblk += J.n_dblk;
+            T.out += J.n_out;
+            T.max_dblk = std::max(T.max_dblk, J.n_dblk);
+        } else {
+            o_lba[j] = A.take(8 * J.n_groups);
+            o_lbb[j] = A.take(8 * J.n_groups);
+            o_woff[j] = A.take(8 * J.n_chunks);
+            o_zoff[j] = A.take(8 * J.n_chunks);
+            o_mm[j] = A.take(8 * std::max<uint64_t>(J.n_mm, J.n_tiles));
+            J.mm_begin = T.mm;
+            J.tune_begin = T.tune;
+            J.tile_begin = T.tiles;
+            J.chunk_begin = T.chunks;
+            J.group_begin = T.groups;
+            T.mm += J.n_mm;
+            T.tune += J.n_tune;
+            T.tiles += J.n_tiles;
+            T.chunks += J.n_chunks;
+            T.groups += J.n_groups;
+            T.max_groups = std::max(T.max_groups, J.n_groups);
+        }
+    }
+    if (T.groups > 0xffffffffull || T.dblk > 0xffffffffull || T.tune > 0xffffffffull)
+        return fail(c, HIZ_ERR_ARG, "batch too large for one launch");
+    hiz_status rc = ensure_ws(c, A.off);
+    if (rc)
+        return rc;
+    const uint64_t job_bytes = ((sizeof(Job) * nj + 255) & ~uint64_t(255));
+    rc = ensure_pinned(c, job_bytes + (uint64_t)kResultBytes * nj + 256);
+    if (rc)
+        return rc;
+    uint8_t *ws = static_cast<uint8_t *>(c->ws);
+    for (int j = 0; j < nj; j++) {
+        Job &J = jobs[j];
+        J.st = reinterpret_cast<FieldState *>(ws + o_st[j]);
+        J.codes = ws + o_codes[j];
+        J.lb_a = reinterpret_cast<uint64_t *>(ws + o_lba[j]);
+        if (decompress) {
+            J.dt = reinterpret_cast<DecTables *>(ws + o_dt[j]);
+        } else {
+            J.lb_b = reinterpret_cast<uint64_t *>(ws + o_lbb[j]);
+            J.woff = reinterpret_cast<uint64_t *>(ws + o_woff[j]);
+            J.zoff = reinterpret_cast<uint64_t *>(ws + o_zoff[j]);
+            J.mm_part = reinterpret_cast<uint2 *>(ws + o_mm[j]);
+        }
+    }
+    memcpy(c->pinned, jobs.data(), sizeof(Job) * nj);
+    L.d_jobs = reinterpret_cast<Job *>(ws + o_jobs);
+    L.d_cnt = reinterpret_cast<Counters *>(ws + o_cnt);
+    L.d_res = ws + o_res;
+    L.h_res = c->pinned + job_bytes;
+    return HIZ_OK;
+}
+
+// The launch sequence of compression (Sec. 5: range and bound, tuner,
+// interpolation + quantization + histogram, codebook, encoding) for all jobs.
+void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int tz,
+                      hipStream_t s, bool prof)
+{
+    hipMemcpyAsync(L.d_jobs, c->pinned, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
+    {
+        Scope sc(c, s, "init", prof);
+        launch_init_compress(L.d_jobs, nj, T.max_groups, L.d_cnt, s);
+    }
+    if (T.mm) {
+        Scope sc(c, s, "minmax", prof);
+        launch_minmax(L.d_jobs, nj, T.mm, c->cus * 8, s);
+    }
+    {
+        Scope sc(c, s, "eps", prof);
+        launch_eps(L.d_jobs, nj, s);
+    }
+    if (T.tune) {
+        Scope sc(c, s, "tune", prof);
+        launch_tune(L.d_jobs, nj, T.tune, s);
+    }
+    {
+        Scope sc(c, s, "tune_pick", prof);
+        launch_tune_pick(L.d_jobs, nj, s);
+    }
+    {
+        Scope sc(c, s, "predict_quant", prof);
+        launch_predict(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, false), s);
+    }
+    {
+        Scope sc(c, s, "codebook", prof);
+        launch_codebook(L.d_jobs, nj, s);
+    }
+    {
+        Scope sc(c, s, "encode", prof);
+        launch_encode(L.d_jobs, nj, T.chunks, T.groups, L.d_cnt, encode_grid(c), s);
+    }
+    launch_gather_results(L.d_jobs, nj, L.d_res, s);
+    hipMemcpyAsync(L.h_res, L.d_res, (size_t)kResultBytes * nj, hipMemcpyDeviceToHost, s);
+}
+
+// The launch sequence of decompression (decode, outliers, reconstruction).
+void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int tz,
+                        hipStream_t s, bool prof)
+{
+    hipMemcpyAsync(L.d_jobs, c->pinned, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
+    {
+        Scope sc(c, s, "init_dec", prof);
+        launch_init_decompress(L.d_jobs, nj, T.max_dblk, L.d_cnt, s);
+    }
+    {
+        Scope sc(c, s, "dec_tables", prof);
+        launch_dec_tables(L.d_jobs, nj, s);
+    }
+    {
+        Scope sc(c, s, "decode", prof);
+        launch_decode(L.d_jobs, nj, T.dblk, L.d_cnt, s);
+    }
+    if (T.out) {
+        Scope sc(c, s, "scatter", prof);
+        launch_scatter(L.d_jobs, nj, T.out, s);
+    }
+    {
+        Scope sc(c, s, "reconstruct", prof);
+        launch_reconstruct(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, true), s);
+    }
+    launch_gather_results(L.d_jobs, nj, L.d_res, s);
+    hipMemcpyAsync(L.h_res, L.d_res, (size_t)kResultBytes * nj, hipMemcpyDeviceToHost, s);
+}
+
+// Run the sequence eagerly, or replay (building on first use) the HIP graph of
+// this launch geometry. Graph replay re-reads the Job table from the same
+// pinned buffer, so only the geometry has to match.
+hiz_status enqueue(hiz_ctx *c, int kind, const Layout &L, int nj, const Totals &T, int tz,
+                   hipStream_t s)
+{
+    if (!c->graphs) {
+        if (kind == 0)
+            enqueue_compress(c, L, nj, T, tz, s, true);
+        else
+            enqueue_decompress(c, L, nj, T, tz, s, true);
+        HIP_TRY(c, hipGetLastError());
+        return HIZ_OK;
+    }
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    key.kind = kind;
+    key.njobs = nj;
+    key.tz = tz;
+    const uint64_t v[12] = {T.mm,  T.tune,     T.tiles,    T.chunks,
+                            T.groups, T.dblk,  T.out,      T.max_groups,
+                            T.max_dblk, (uint64_t)c->cus, 0, 0};
+    memcpy(key.v, v, sizeof(v));
+    key.ws = c->ws;
+    key.pinned = c->pinned;
+    // occupancy queries stay outside the capture
+    predict_grid(c, tz, 1, kind == 1);
+    encode_grid(c);
+    GraphSlot *hit = nullptr;
+    for (GraphSlot &g : c->gslot)
+        if (g.exec && memcmp(&g.key, &key, sizeof(key)) == 0)
+            hit = &g;
+    if (!hit) {
+        if (!c->cap_stream)
+            HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        GraphSlot *victim = &c->gslot[0];
+        for (GraphSlot &g : c->gslot)
+            if (!g.exec || g.used < victim->used)
+                victim = &g;
+        if (victim->exec) {
+            hipGraphExecDestroy(victim->exec);
+            victim->exec = nullptr;
+        }
+        HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        if (kind == 0)
+            enqueue_compress(c, L, nj, T, tz, c->cap_stream, false);
+        else
+            enqueue_decompress(c, L, nj, T, tz, c->cap_stream, false);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (e != hipSuccess || !g) {
+            hipGetLastError();
+            return fail(c, HIZ_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        }
+        e = hipGraphInstantiate(&victim->exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            victim->exec = nullptr;
+            hipGetLastError();
+            return fail(c, HIZ_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        victim->key = key;
+        hit = victim;
+        c->graph_builds++;
+    }
+    hit->used = ++c->gclock;
+    {
+        Scope sc(c, s, kind == 0 ? "graph_compress" : "graph_decompress");
+        HIP_TRY(c, hipGraphLaunch(hit->exec, s));
+    }
+    c->graph_replays++;
+    return HIZ_OK;
+}
+
+void begin_batch(hiz_ctx *c, int kind, int n, hipStream_t s)
+{
+    Batch &B = c->batch;
+    B.kind = kind;
+    B.n = n;
+    B.njobs = 0;
+    B.field.clear();
+    B.status.assign(n, HIZ_OK);
+    B.size.assign(n, 0);
+    B.cap.assign(n, 0);
+    B.dims.assign(3 * (size_t)n, 0);
+    B.n_out.clear();
+    B.msg.assign(n, std::string());
+    B.s = s;
+    B.h_res = nullptr;
+}
+
+// A submission that failed after enqueueing part of its work: let that work
+// drain so that nothing still reads the context's buffers.
+hiz_status abandon(hiz_ctx *c, hipStream_t s, hiz_status rc)
+{
+    std::string keep = c->err;
+    hipStreamSynchronize(s);
+    hipGetLastError();
+    c->err = keep;
+    return rc;
+}
+
+hiz_status mark_submitted(hiz_ctx *c)
+{
+    if (!c->done)
+        HIP_TRY(c, hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+    HIP_TRY(c, hipEventRecord(c->done, c->batch.s));
+    c->batch.pending = true;
+    return HIZ_OK;
+}
+
+hiz_status submit_compress(hiz_ctx *c, int n, const float *const *d_fields, const uint64_t *dims,
+                           const int *modes, const double *ebs, const hiz_params *params,
+                           void *const *d_outs, const uint64_t *caps, hipStream_t s)
+{
+    c->err.clear();
+    if (n < 0 || n > kMaxBatch)
+        return fail(c, HIZ_ERR_ARG, "batch size must be in [0, %d]", kMaxBatch);
+    if (n > 0 && (!d_fields || !dims || !modes || !ebs || !d_outs || !caps))
+        return fail(c, HIZ_ERR_ARG, "NULL argument");
+    if (c->batch.pending)
+        return fail(c, HIZ_ERR_ARG, "the previous batch on this context is not finished");
+    hiz_params p;
+    int tz;
+    hiz_status rc = resolve_params(c, params, p, tz);
+    if (rc)
+        return rc;
+    HIP_TRY(c, hipSetDevice(c->device));
+    begin_batch(c, 0, n, s);
+    Batch &B = c->batch;
+    std::vector<Job> jobs;
+    jobs.reserve(n);
+    for (int i = 0; i < n; i++) {
+        Job J;
+        B.cap[i] = caps[i];
+        B.status[i] = plan_compress(d_fields[i], dims + 3 * i, modes[i], ebs[i], p, tz, d_outs[i],
+                                    caps[i], J, B.msg[i]);
+        if (B.status[i] == HIZ_OK) {
+            jobs.push_back(J);
+            B.field.push_back(i);
+        }
+    }
+    B.njobs = (int)jobs.size();
+    if (B.njobs) {
+        Totals T;
+        Layout L;
+        rc = layout(c, jobs, false, T, L);
+        if (rc)
+            return abandon(c, s, rc);
+        B.h_res = L.h_res;
+        rc = enqueue(c, 0, L, B.njobs, T, tz, s);
+        if (rc)
+            return abandon(c, s, rc);
+    }
+    rc = mark_submitted(c);
+    return rc ? abandon(c, s, rc) : rc;
+}
+
+hiz_status submit_decompress(hiz_ctx *c, int n, const void *const *d_ins,
+                             const uint64_t *in_sizes, float *const *d_fields,
+                             const uint64_t *field_caps, hipStream_t s)
+{
+    c->err.clear();
+    if (n < 0 || n > kMaxBatch)
+        return fail(c, HIZ_ERR_ARG, "batch size must be in [0, %d]", kMaxBatch);
+    if (n > 0 && (!d_ins || !in_sizes || !d_fields || !field_caps))
+        return fail(c, HIZ_ERR_ARG, "NULL argument");
+    if (c->batch.pending)
+        return fail(c, HIZ_ERR_ARG, "the previous batch on this context is not finished");
+    HIP_TRY(c, hipSetDevice(c->device));
+    begin_batch(c, 1, n, s);
+    Batch &B = c->batch;
+    const int tz = kDefaultTileZ;
+    // headers and code-length tables of every stream, in one synchronization
+    hiz_status rc = ensure_pinned(c, (uint64_t)kOffChunks * std::max(n, 1));
+    if (rc)
+        return rc;
+    std::vector<uint64_t> nh(n, 0);
+    for (int i = 0; i < n; i++) {
+        if (!d_ins[i] || !d_fields[i]) {
+            B.status[i] = HIZ_ERR_ARG;
+            B.msg[i] = "NULL argument";
+            continue;
+        }
+        if ((reinterpret_cast<uintptr_t>(d_fields[i]) & 3) ||
+            (reinterpret_cast<uintptr_t>(d_ins[i]) & 15)) {
+            B.status[i] = HIZ_ERR_ARG;
+            B.msg[i] = "field must be 4-byte and stream 16-byte aligned";
+            continue;
+        }
+        nh[i] = std::min<uint64_t>(in_sizes[i], kOffChunks);
+        if (nh[i] < (uint64_t)kHdrBytes) {
+            B.status[i] = HIZ_ERR_CORRUPT;
+            B.msg[i] = "stream shorter than its header";
+            continue;
+        }
+        if (hipMemcpyAsync(c->pinned + (uint64_t)kOffChunks * i, d_ins[i], nh[i],
+                           hipMemcpyDeviceToHost, s) != hipSuccess)
+            return abandon(c, s, fail(c, HIZ_ERR_HIP, "cannot read the header of stream %d", i));
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    std::vector<Parsed> P(n);
+    std::vector<Job> jobs;
+    for (int i = 0; i < n; i++) {
+        if (B.status[i])
+            continue;
+        B.cap[i] = field_caps[i];
+        hiz_status st = parse_header(&B.msg[i], c->pinned + (uint64_t)kOffChunks * i, nh[i],
+                                     in_sizes[i], &P[i]);
+        if (st == HIZ_OK && !P[i].info.constant && nh[i] < (uint64_t)kOffChunks) {
+            st = HIZ_ERR_CORRUPT;
+            B.msg[i] = "stream shorter than its tables";
+        }
+        if (st == HIZ_OK && field_caps[i] < P[i].N) {
+            st = HIZ_ERR_BUFSZ;
+            B.msg[i] = fmt_msg("field needs %llu elements", (unsigned long long)P[i].N);
+        }
+        B.status[i] = st;
+        B.size[i] = P[i].N;
+        if (st == HIZ_OK || st == HIZ_ERR_BUFSZ)
+            for (int k = 0; k < 3; k++)
+                B.dims[3 * i + k] = P[i].info.dims[k];
+    }
+    // constant streams: one fill each (their device work is done here)
+    for (int i = 0; i < n; i++) {
+        if (B.status[i] || !P[i].info.constant)
+            continue;
+        Scope sc(c, s, "fill");
+        launch_fill(d_fields[i], P[i].N, P[i].const_value, s);
+    }
+    for (int i = 0; i < n; i++) {
+        if (B.status[i] || P[i].info.constant)
+            continue;
+        Job J;
+        plan_decompress(P[i], d_ins[i], in_sizes[i], d_fields[i], tz, J);
+        jobs.push_back(J);
+        B.field.push_back(i);
+        B.n_out.push_back(J.n_out);
+    }
+    if (hipGetLastError() != hipSuccess)
+        return abandon(c, s, fail(c, HIZ_ERR_HIP, "fill launch failed"));
+    B.njobs = (int)jobs.size();
+    if (B.njobs) {
+        Totals T;
+        Layout L;
+        rc = layout(c, jobs, true, T, L);
+        if (rc)
+            return abandon(c, s, rc);
+        B.h_res = L.h_res;
+        rc = enqueue(c, 1, L, B.njobs, T, tz, s);
+        if (rc)
+            return abandon(c, s, rc);
+    }
+    rc = mark_submitted(c);
+    return rc ? abandon(c, s, rc) : rc;
+}
+
+// Wait for the pending batch and turn its device results into per-field
+// statuses and sizes. Returns the first failing field's status.
+hiz_status finish(hiz_ctx *c, uint64_t *sizes, uint64_t *dims, hiz_status *statuses)
+{
+    Batch &B = c->batch;
+    if (!B.pending)
+        return fail(c, HIZ_ERR_ARG, "no batch is pending on this context");
+    B.pending = false;
+    HIP_TRY(c, hipEventSynchronize(c->done));
+    if (c->profiling)
+        collect_profile(c);
+    for (int j = 0; j < B.njobs; j++) {
+        const int i = B.field[j];
+        FieldState res;
+        memcpy(&res, B.h_res + (size_t)kResultBytes * j, kResultBytes);
+        if (B.kind == 0) {
+            if (res.flags & ST_NONFINITE) {
+                B.status[i] = HIZ_ERR_NONFINITE;
+                B.msg[i] = "field holds NaN or Inf";
+                continue;
+            }
+            if (res.flags & ST_CORRUPT) {
+                B.status[i] = HIZ_ERR_HIP;
+                B.msg[i] = "internal consistency check failed";
+                continue;
+            }
+            B.size[i] = res.total_bytes;
+            if ((res.flags & ST_OVERFLOW) || res.total_bytes > B.cap[i]) {
+                B.status[i] = HIZ_ERR_BUFSZ;
+                B.msg[i] = fmt_msg("output needs %llu bytes, capacity is %llu",
+                                   (unsigned long long)res.total_bytes,
+                                   (unsigned long long)B.cap[i]);
+            }
+        } else if ((res.flags & ST_CORRUPT) || res.zeros_seen != B.n_out[j]) {
+            B.status[i] = HIZ_ERR_CORRUPT;
+            B.msg[i] = "stream failed a decoding check";
+        }
+    }
+    hiz_status first = HIZ_OK;
+    for (int i = 0; i < B.n; i++) {
+        if (sizes)
+            sizes[i] = B.size[i];
+        if (dims)
+            for (int k = 0; k < 3; k++)
+                dims[3 * i + k] = B.dims[3 * i + k];
+        if (statuses)
+            statuses[i] = B.status[i];
+        if (B.status[i] && first == HIZ_OK) {
+            first = B.status[i];
+            if (B.n == 1)
+                c->err = B.msg[i];
+            else
+                c->err = fmt_msg("field %d: %s", i, B.msg[i].c_str());
+        }
+    }
+    return first;
 }
 
 } // namespace
@@ -390,8 +1081,13 @@ void hiz_destroy(hiz_ctx *c)
         return;
     hipSetDevice(c->device);
     hipDeviceSynchronize();
+    drop_graphs(c);
     for (hipEvent_t e : c->events)
         hipEventDestroy(e);
+    if (c->done)
+        hipEventDestroy(c->done);
+    if (c->cap_stream)
+        hipStreamDestroy(c->cap_stream);
     if (c->ws)
         hipFree(c->ws);
     if (c->pinned)
@@ -443,162 +1139,114 @@ void hiz_reset_profile(hiz_ctx *c)
         c->stats.clear();
 }
 
+hiz_status hiz_set_graphs(hiz_ctx *c, int on)
+{
+    if (!c)
+        return HIZ_ERR_ARG;
+    if (c->batch.pending)
+        return fail(c, HIZ_ERR_ARG, "a batch is pending on this context");
+    c->graphs = on != 0;
+    return HIZ_OK;
+}
+
+void hiz_graph_stats(const hiz_ctx *c, uint64_t *builds, uint64_t *replays)
+{
+    if (builds)
+        *builds = c ? c->graph_builds : 0;
+    if (replays)
+        *replays = c ? c->graph_replays : 0;
+}
+
 hiz_status hiz_compress(hiz_ctx *c, const float *d_field, const uint64_t dims[3],
                         hiz_eb_mode mode, double eb, const hiz_params *params, void *d_out,
                         uint64_t out_cap, uint64_t *out_size, hiz_stream_t stream)
 {
     if (!c)
         return HIZ_ERR_ARG;
-    c->err.clear();
-    if (!d_field || !dims || !d_out || !out_size)
+    if (!out_size || !dims)
         return fail(c, HIZ_ERR_ARG, "NULL argument");
     *out_size = 0;
-    if (mode != HIZ_ABS && mode != HIZ_REL)
-        return fail(c, HIZ_ERR_ARG, "bad error-bound mode");
-    if (!(eb > 0.0) || !std::isfinite(eb))
-        return fail(c, HIZ_ERR_ARG, "error bound must be finite and positive");
-    if ((reinterpret_cast<uintptr_t>(d_field) & 3) || (reinterpret_cast<uintptr_t>(d_out) & 15))
-        return fail(c, HIZ_ERR_ARG, "field must be 4-byte and stream 16-byte aligned");
-    uint64_t N = 1;
-    for (int k = 0; k < 3; k++) {
-        if (dims[k] == 0 || dims[k] > kMaxN || N > kMaxN / dims[k])
-            return fail(c, HIZ_ERR_ARG, "bad dims");
-        N *= dims[k];
-    }
-    hiz_params p;
-    memset(&p, 0, sizeof(p));
-    p.tune = 1;
-    for (int l = 0; l < 4; l++)
-        p.level_cfg[l][0] = HIZ_SPLINE_CUBIC;
-    if (params)
-        p = *params;
-    if (!valid_cfg(p.level_cfg))
-        return fail(c, HIZ_ERR_ARG, "bad level configuration");
-    uint32_t chunk = p.chunk ? p.chunk : default_chunk(N);
-    if (chunk < 256 || chunk > 65536 || (chunk & (chunk - 1)))
-        return fail(c, HIZ_ERR_ARG, "chunk must be a power of two in [256, 65536]");
-    int tz = p.tile_z ? (int)p.tile_z : kDefaultTileZ;
-    if (tz != 1 && tz != 2 && tz != 4)
-        return fail(c, HIZ_ERR_ARG, "tile_z must be 1, 2 or 4");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    HIP_TRY(c, hipSetDevice(c->device));
+    const int m = (int)mode;
+    void *outs[1] = {d_out};
+    hiz_status rc = submit_compress(c, 1, &d_field, dims, &m, &eb, params, outs, &out_cap,
+                                    reinterpret_cast<hipStream_t>(stream));
+    return rc ? rc : finish(c, out_size, nullptr, nullptr);
+}
 
-    Job J;
-    memset(&J, 0, sizeof(J));
-    J.field = d_field;
-    J.stream = static_cast<uint8_t *>(d_out);
-    J.cap = out_cap;
-    for (int k = 0; k < 3; k++) {
-        J.dims[k] = dims[k];
-        J.nb[k] = (uint32_t)cdiv(dims[k], kAnchor);
-        J.n_full[k] = dims[k] >= (uint64_t)kSide ? (uint32_t)((dims[k] - kSide) / kAnchor + 1) : 0;
-    }
-    J.N = N;
-    J.ntz = (uint32_t)cdiv(J.nb[2], tz);
-    J.n_anchors = (uint64_t)J.nb[0] * J.nb[1] * J.nb[2];
-    J.chunk = chunk;
-    J.log2_chunk = (uint32_t)ilog2(chunk);
-    J.n_chunks = cdiv(N, chunk);
-    J.off_anchors = align16(kOffChunks + 4 * J.n_chunks);
-    J.mode = mode;
-    J.tune = p.tune ? 1 : 0;
-    J.eb = eb;
-    memcpy(J.cfg_forced, p.level_cfg, sizeof(J.cfg_forced));
-    J.idx_bytes = N < (1ull << 32) ? 4 : 8;
-    J.n_mm = mode == HIZ_REL ? cdiv(N, 16384) : 0;
-    const uint64_t n_full = (uint64_t)J.n_full[0] * J.n_full[1] * J.n_full[2];
-    if (J.tune && n_full > 0) {
-        uint64_t ns = std::max<uint64_t>(1, cdiv(2 * N, 1000ull * 4913ull));
-        J.n_samples = (uint32_t)std::min<uint64_t>(ns, n_full);
-    }
-    J.n_tune = (uint64_t)J.n_samples * 9;
-    J.n_tiles = (uint64_t)J.nb[0] * J.nb[1] * J.ntz;
-
-    Arena A;
-    const uint64_t o_job = A.take(sizeof(Job));
-    const uint64_t o_st = A.take(sizeof(FieldState));
-    const uint64_t o_cnt = A.take(sizeof(Counters));
-    const uint64_t o_codes = A.take(N);
-    J.n_groups = cdiv(J.n_chunks, kEncGroupChunks);
-    const uint64_t o_lba = A.take(8 * J.n_groups);
-    const uint64_t o_lbb = A.take(8 * J.n_groups);
-    const uint64_t o_woff = A.take(8 * J.n_chunks);
-    const uint64_t o_zoff = A.take(8 * J.n_chunks);
-    const uint64_t o_mm = A.take(8 * std::max<uint64_t>(J.n_mm, J.n_tiles));
-    hiz_status rc = ensure_ws(c, A.off);
+hiz_status hiz_decompress(hiz_ctx *c, const void *d_in, uint64_t in_size, float *d_field,
+                          uint64_t field_cap, uint64_t dims_out[3], hiz_stream_t stream)
+{
+    if (!c)
+        return HIZ_ERR_ARG;
+    hiz_status rc = submit_decompress(c, 1, &d_in, &in_size, &d_field, &field_cap,
+                                      reinterpret_cast<hipStream_t>(stream));
     if (rc)
         return rc;
-    rc = ensure_pinned(c, sizeof(Job) + kResultBytes + 256);
-    if (rc)
-        return rc;
-    uint8_t *ws = static_cast<uint8_t *>(c->ws);
-    J.st = reinterpret_cast<FieldState *>(ws + o_st);
-    J.codes = ws + o_codes;
-    J.lb_a = reinterpret_cast<uint64_t *>(ws + o_lba);
-    J.lb_b = reinterpret_cast<uint64_t *>(ws + o_lbb);
-    J.mm_part = reinterpret_cast<uint2 *>(ws + o_mm);
-    J.woff = reinterpret_cast<uint64_t *>(ws + o_woff);
-    J.zoff = reinterpret_cast<uint64_t *>(ws + o_zoff);
-    Job *d_job = reinterpret_cast<Job *>(ws + o_job);
-    Counters *d_cnt = reinterpret_cast<Counters *>(ws + o_cnt);
-    memcpy(c->pinned, &J, sizeof(J));
-    uint8_t *h_res = c->pinned + ((sizeof(Job) + 255) & ~size_t(255));
+    uint64_t dims[3] = {0, 0, 0};
+    rc = finish(c, nullptr, dims, nullptr);
+    if (dims_out && dims[0])
+        memcpy(dims_out, dims, sizeof(dims));
+    return rc;
+}
 
-    HIP_TRY(c, hipMemcpyAsync(d_job, c->pinned, sizeof(Job), hipMemcpyHostToDevice, s));
-    {
-        Scope sc(c, s, "init");
-        launch_init_compress(d_job, 1, J.n_groups, d_cnt, s);
-    }
-    if (J.n_mm) {
-        Scope sc(c, s, "minmax");
-        launch_minmax(d_job, 1, J.n_mm, c->cus * 8, s);
-    }
-    {
-        Scope sc(c, s, "eps");
-        launch_eps(d_job, 1, s);
-    }
-    if (J.n_tune) {
-        Scope sc(c, s, "tune");
-        launch_tune(d_job, 1, J.n_tune, s);
-    }
-    {
-        Scope sc(c, s, "tune_pick");
-        launch_tune_pick(d_job, 1, s);
-    }
-    {
-        Scope sc(c, s, "predict_quant");
-        launch_predict(d_job, 1, J.n_tiles, tz, predict_grid(c, tz, J.n_tiles, false), s);
-    }
-    {
-        Scope sc(c, s, "codebook");
-        launch_codebook(d_job, 1, s);
-    }
-    {
-        if (!c->enc_bpc) {
-            c->enc_bpc = encode_blocks_per_cu();
-            if (debug_on())
-                fprintf(stderr, "[hiz] encode: %d CUs x %d workgroups per CU\n", c->cus,
-                        c->enc_bpc);
-        }
-        Scope sc(c, s, "encode");
-        launch_encode(d_job, 1, J.n_chunks, J.n_groups, d_cnt, c->cus * c->enc_bpc, s);
-    }
-    HIP_TRY(c, hipGetLastError());
-    HIP_TRY(c, hipMemcpyAsync(h_res, J.st, kResultBytes, hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    if (c->profiling)
-        collect_profile(c);
-    FieldState res;
-    memcpy(&res, h_res, kResultBytes);
-    if (res.flags & ST_NONFINITE)
-        return fail(c, HIZ_ERR_NONFINITE, "field holds NaN or Inf");
-    if (res.flags & ST_CORRUPT)
-        return fail(c, HIZ_ERR_HIP, "internal consistency check failed");
-    *out_size = res.total_bytes;
-    if ((res.flags & ST_OVERFLOW) || res.total_bytes > out_cap)
-        return fail(c, HIZ_ERR_BUFSZ, "output needs %llu bytes, capacity is %llu",
-                    (unsigned long long)res.total_bytes, (unsigned long long)out_cap);
-    return HIZ_OK;
+hiz_status hiz_compress_batch_submit(hiz_ctx *c, int n, const float *const *d_fields,
+                                     const uint64_t *dims, const int *modes, const double *ebs,
+                                     const hiz_params *params, void *const *d_outs,
+                                     const uint64_t *out_caps, hiz_stream_t stream)
+{
+    if (!c)
+        return HIZ_ERR_ARG;
+    return submit_compress(c, n, d_fields, dims, modes, ebs, params, d_outs, out_caps,
+                           reinterpret_cast<hipStream_t>(stream));
+}
+
+hiz_status hiz_decompress_batch_submit(hiz_ctx *c, int n, const void *const *d_ins,
+                                       const uint64_t *in_sizes, float *const *d_fields,
+                                       const uint64_t *field_caps, hiz_stream_t stream)
+{
+    if (!c)
+        return HIZ_ERR_ARG;
+    return submit_decompress(c, n, d_ins, in_sizes, d_fields, field_caps,
+                             reinterpret_cast<hipStream_t>(stream));
+}
+
+int hiz_batch_ready(hiz_ctx *c)
+{
+    if (!c || !c->batch.pending)
+        return 1;
+    return hipEventQuery(c->done) == hipSuccess ? 1 : 0;
+}
+
+hiz_status hiz_batch_finish(hiz_ctx *c, uint64_t *sizes, uint64_t *dims, hiz_status *statuses)
+{
+    if (!c)
+        return HIZ_ERR_ARG;
+    return finish(c, sizes, dims, statuses);
+}
+
+hiz_status hiz_compress_batch(hiz_ctx *c, int n, const float *const *d_fields,
+                              const uint64_t *dims, const int *modes, const double *ebs,
+                              const hiz_params *params, void *const *d_outs,
+                              const uint64_t *out_caps, uint64_t *out_sizes,
+                              hiz_status *statuses, hiz_stream_t stream)
+{
+    if (!c)
+        return HIZ_ERR_ARG;
+    hiz_status rc = submit_compress(c, n, d_fields, dims, modes, ebs, params, d_outs, out_caps,
+                                    reinterpret_cast<hipStream_t>(stream));
+    return rc ? rc : finish(c, out_sizes, nullptr, statuses);
+}
+
+hiz_status hiz_decompress_batch(hiz_ctx *c, int n, const void *const *d_ins,
+                                const uint64_t *in_sizes, float *const *d_fields,
+                                const uint64_t *field_caps, uint64_t *dims_out,
+                                hiz_status *statuses, hiz_stream_t stream)
+{
+    if (!c)
+        return HIZ_ERR_ARG;
+    hiz_status rc = submit_decompress(c, n, d_ins, in_sizes, d_fields, field_caps,
+                                      reinterpret_cast<hipStream_t>(stream));
+    return rc ? rc : finish(c, nullptr, dims_out, statuses);
 }
 
 hiz_status hiz_inspect(const void *h_stream, uint64_t n, hiz_info *out)
@@ -612,134 +1260,6 @@ hiz_status hiz_inspect(const void *h_stream, uint64_t n, hiz_info *out)
     if (rc)
         return rc;
     *out = P.info;
-    return HIZ_OK;
-}
-
-hiz_status hiz_decompress(hiz_ctx *c, const void *d_in, uint64_t in_size, float *d_field,
-                          uint64_t field_cap, uint64_t dims_out[3], hiz_stream_t stream)
-{
-    if (!c)
-        return HIZ_ERR_ARG;
-    c->err.clear();
-    if (!d_in || !d_field)
-        return fail(c, HIZ_ERR_ARG, "NULL argument");
-    if ((reinterpret_cast<uintptr_t>(d_field) & 3) || (reinterpret_cast<uintptr_t>(d_in) & 15))
-        return fail(c, HIZ_ERR_ARG, "field must be 4-byte and stream 16-byte aligned");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    HIP_TRY(c, hipSetDevice(c->device));
-    hiz_status rc = ensure_pinned(c, 4096);
-    if (rc)
-        return rc;
-    const uint64_t nh = std::min<uint64_t>(in_size, kOffChunks);
-    if (nh < (uint64_t)kHdrBytes)
-        return fail(c, HIZ_ERR_CORRUPT, "stream shorter than its header");
-    HIP_TRY(c, hipMemcpyAsync(c->pinned, d_in, nh, hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    Parsed P;
-    rc = parse_header(c, c->pinned, nh, in_size, &P);
-    if (rc)
-        return rc;
-    if (P.info.constant == 0 && nh < (uint64_t)kOffChunks)
-        return fail(c, HIZ_ERR_CORRUPT, "stream shorter than its tables");
-    if (dims_out)
-        for (int k = 0; k < 3; k++)
-            dims_out[k] = P.info.dims[k];
-    if (field_cap < P.N)
-        return fail(c, HIZ_ERR_BUFSZ, "field needs %llu elements", (unsigned long long)P.N);
-    if (P.info.constant) {
-        {
-            Scope sc(c, s, "fill");
-            launch_fill(d_field, P.N, P.const_value, s);
-        }
-        HIP_TRY(c, hipGetLastError());
-        HIP_TRY(c, hipStreamSynchronize(s));
-        if (c->profiling)
-            collect_profile(c);
-        return HIZ_OK;
-    }
-    const int tz = kDefaultTileZ;
-    Job J;
-    memset(&J, 0, sizeof(J));
-    J.out = d_field;
-    J.stream = const_cast<uint8_t *>(static_cast<const uint8_t *>(d_in));
-    J.cap = in_size;
-    for (int k = 0; k < 3; k++) {
-        J.dims[k] = P.info.dims[k];
-        J.nb[k] = (uint32_t)cdiv(J.dims[k], kAnchor);
-    }
-    J.N = P.N;
-    J.ntz = (uint32_t)cdiv(J.nb[2], tz);
-    J.n_anchors = (uint64_t)J.nb[0] * J.nb[1] * J.nb[2];
-    J.chunk = P.info.chunk;
-    J.log2_chunk = (uint32_t)ilog2(J.chunk);
-    J.n_chunks = P.info.n_chunks;
-    J.off_anchors = P.off_anchors;
-    J.mode = P.info.mode;
-    J.eb = P.info.eb;
-    memcpy(J.cfg_forced, P.info.level_cfg, sizeof(J.cfg_forced));
-    J.idx_bytes = (uint8_t)P.idx_bytes;
-    J.n_tiles = (uint64_t)J.nb[0] * J.nb[1] * J.ntz;
-    J.n_dblk = cdiv(J.n_chunks, 256);
-    J.off_oidx = P.off_oidx;
-    J.off_oval = P.off_oval;
-    J.off_payload = P.off_payload;
-    J.n_out = P.info.n_outliers;
-    J.payload_words = P.info.payload_words;
-    J.eps = P.info.eps;
-
-    Arena A;
-    const uint64_t o_job = A.take(sizeof(Job));
-    const uint64_t o_st = A.take(sizeof(FieldState));
-    const uint64_t o_cnt = A.take(sizeof(Counters));
-    const uint64_t o_dt = A.take(sizeof(DecTables));
-    const uint64_t o_codes = A.take(J.N);
-    const uint64_t o_lba = A.take(8 * J.n_dblk);
-    rc = ensure_ws(c, A.off);
-    if (rc)
-        return rc;
-    rc = ensure_pinned(c, sizeof(Job) + kResultBytes + 256);
-    if (rc)
-        return rc;
-    uint8_t *ws = static_cast<uint8_t *>(c->ws);
-    J.st = reinterpret_cast<FieldState *>(ws + o_st);
-    J.dt = reinterpret_cast<DecTables *>(ws + o_dt);
-    J.codes = ws + o_codes;
-    J.lb_a = reinterpret_cast<uint64_t *>(ws + o_lba);
-    Job *d_job = reinterpret_cast<Job *>(ws + o_job);
-    Counters *d_cnt = reinterpret_cast<Counters *>(ws + o_cnt);
-    memcpy(c->pinned, &J, sizeof(J));
-    uint8_t *h_res = c->pinned + ((sizeof(Job) + 255) & ~size_t(255));
-
-    HIP_TRY(c, hipMemcpyAsync(d_job, c->pinned, sizeof(Job), hipMemcpyHostToDevice, s));
-    {
-        Scope sc(c, s, "init_dec");
-        launch_init_decompress(d_job, 1, J.n_dblk, d_cnt, s);
-    }
-    {
-        Scope sc(c, s, "dec_tables");
-        launch_dec_tables(d_job, 1, s);
-    }
-    {
-        Scope sc(c, s, "decode");
-        launch_decode(d_job, 1, J.n_dblk, d_cnt, s);
-    }
-    if (J.n_out) {
-        Scope sc(c, s, "scatter");
-        launch_scatter(d_job, 1, J.n_out, s);
-    }
-    {
-        Scope sc(c, s, "reconstruct");
-        launch_reconstruct(d_job, 1, J.n_tiles, tz, predict_grid(c, tz, J.n_tiles, true), s);
-    }
-    HIP_TRY(c, hipGetLastError());
-    HIP_TRY(c, hipMemcpyAsync(h_res, J.st, kResultBytes, hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    if (c->profiling)
-        collect_profile(c);
-    FieldState res;
-    memcpy(&res, h_res, kResultBytes);
-    if ((res.flags & ST_CORRUPT) || res.zeros_seen != J.n_out)
-        return fail(c, HIZ_ERR_CORRUPT, "stream failed a decoding check");
     return HIZ_OK;
 }
 

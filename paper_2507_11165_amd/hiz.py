@@ -22,8 +22,10 @@ _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NONFINITE", 3: "ERR_BUFSZ", 4: "ERR_CO
 
 # exported symbols (kept in step with include/hiz.h)
 SYMBOLS = ["hiz_create", "hiz_destroy", "hiz_last_error", "hiz_compress_bound", "hiz_compress",
-           "hiz_decompress", "hiz_inspect", "hiz_set_profiling", "hiz_get_profile",
-           "hiz_reset_profile"]
+           "hiz_decompress", "hiz_inspect", "hiz_compress_batch", "hiz_decompress_batch",
+           "hiz_compress_batch_submit", "hiz_decompress_batch_submit", "hiz_batch_ready",
+           "hiz_batch_finish", "hiz_set_graphs", "hiz_graph_stats", "hiz_set_profiling",
+           "hiz_get_profile", "hiz_reset_profile"]
 
 
 class Params(C.Structure):
@@ -78,6 +80,22 @@ def lib():
             L.hiz_decompress.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                          C.c_uint64, u64p, C.c_void_p]
             L.hiz_inspect.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Info)]
+            vpp = C.POINTER(C.c_void_p)
+            ip = C.POINTER(C.c_int)
+            dp = C.POINTER(C.c_double)
+            L.hiz_compress_batch.argtypes = [C.c_void_p, C.c_int, vpp, u64p, ip, dp,
+                                             C.POINTER(Params), vpp, u64p, u64p, ip, C.c_void_p]
+            L.hiz_decompress_batch.argtypes = [C.c_void_p, C.c_int, vpp, u64p, vpp, u64p, u64p,
+                                               ip, C.c_void_p]
+            L.hiz_compress_batch_submit.argtypes = [C.c_void_p, C.c_int, vpp, u64p, ip, dp,
+                                                    C.POINTER(Params), vpp, u64p, C.c_void_p]
+            L.hiz_decompress_batch_submit.argtypes = [C.c_void_p, C.c_int, vpp, u64p, vpp, u64p,
+                                                      C.c_void_p]
+            L.hiz_batch_ready.argtypes = [C.c_void_p]
+            L.hiz_batch_finish.argtypes = [C.c_void_p, u64p, u64p, ip]
+            L.hiz_set_graphs.argtypes = [C.c_void_p, C.c_int]
+            L.hiz_graph_stats.argtypes = [C.c_void_p, u64p, u64p]
+            L.hiz_graph_stats.restype = None
             L.hiz_set_profiling.argtypes = [C.c_void_p, C.c_int]
             L.hiz_set_profiling.restype = None
             L.hiz_get_profile.argtypes = [C.c_void_p, C.POINTER(KernelStat), C.c_int]
@@ -226,6 +244,129 @@ class Context:
         self.decompress_ptr(stream_t.data_ptr(), stream_t.numel(), out.data_ptr(), out.numel(),
                             _stream_handle(stream))
         return out.view(shape) if out.numel() == n else out
+
+    # -- batches (C-ABI shaped: lists of device pointers) --
+    def compress_batch_ptr(self, field_ptrs, shapes, modes, ebs, out_ptrs, out_caps,
+                           params=None, stream_handle=None, submit_only=False):
+        """Compress n fields in one launch per stage. Returns (sizes, statuses), or
+        None when submit_only (then call batch_finish)."""
+        n = len(field_ptrs)
+        fp = (C.c_void_p * max(n, 1))(*field_ptrs)
+        dims = (C.c_uint64 * max(3 * n, 1))(*[int(v) for sh in shapes for v in sh])
+        md = (C.c_int * max(n, 1))(*[_mode(m) for m in modes])
+        eb = (C.c_double * max(n, 1))(*[float(e) for e in ebs])
+        op = (C.c_void_p * max(n, 1))(*out_ptrs)
+        cp = (C.c_uint64 * max(n, 1))(*[int(c) for c in out_caps])
+        p = C.byref(params) if params is not None else None
+        if submit_only:
+            rc = lib().hiz_compress_batch_submit(self._h, n, fp, dims, md, eb, p, op, cp,
+                                                 stream_handle)
+            if rc:
+                raise self._err(rc, "compress_batch_submit")
+            return None
+        sizes = (C.c_uint64 * max(n, 1))()
+        st = (C.c_int * max(n, 1))()
+        rc = lib().hiz_compress_batch(self._h, n, fp, dims, md, eb, p, op, cp, sizes, st,
+                                      stream_handle)
+        if rc and not any(st[i] for i in range(n)):
+            raise self._err(rc, "compress_batch")
+        return [int(sizes[i]) for i in range(n)], [int(st[i]) for i in range(n)]
+
+    def decompress_batch_ptr(self, in_ptrs, in_sizes, out_ptrs, out_caps, stream_handle=None,
+                             submit_only=False):
+        """Decompress n streams in one launch per stage. Returns (dims, statuses), or
+        None when submit_only (then call batch_finish)."""
+        n = len(in_ptrs)
+        ip_ = (C.c_void_p * max(n, 1))(*in_ptrs)
+        isz = (C.c_uint64 * max(n, 1))(*[int(v) for v in in_sizes])
+        op = (C.c_void_p * max(n, 1))(*out_ptrs)
+        cp = (C.c_uint64 * max(n, 1))(*[int(c) for c in out_caps])
+        if submit_only:
+            rc = lib().hiz_decompress_batch_submit(self._h, n, ip_, isz, op, cp, stream_handle)
+            if rc:
+                raise self._err(rc, "decompress_batch_submit")
+            return None
+        dims = (C.c_uint64 * max(3 * n, 1))()
+        st = (C.c_int * max(n, 1))()
+        rc = lib().hiz_decompress_batch(self._h, n, ip_, isz, op, cp, dims, st, stream_handle)
+        if rc and not any(st[i] for i in range(n)):
+            raise self._err(rc, "decompress_batch")
+        return ([tuple(int(dims[3 * i + k]) for k in range(3)) for i in range(n)],
+                [int(st[i]) for i in range(n)])
+
+    def batch_ready(self) -> bool:
+        return bool(lib().hiz_batch_ready(self._h))
+
+    def batch_finish(self, n):
+        """Wait for the pending batch of n fields: (sizes, dims, statuses)."""
+        sizes = (C.c_uint64 * max(n, 1))()
+        dims = (C.c_uint64 * max(3 * n, 1))()
+        st = (C.c_int * max(n, 1))()
+        rc = lib().hiz_batch_finish(self._h, sizes, dims, st)
+        if rc and not any(st[i] for i in range(n)):
+            raise self._err(rc, "batch_finish")
+        return ([int(sizes[i]) for i in range(n)],
+                [tuple(int(dims[3 * i + k]) for k in range(3)) for i in range(n)],
+                [int(st[i]) for i in range(n)])
+
+    def set_graphs(self, on: bool):
+        rc = lib().hiz_set_graphs(self._h, 1 if on else 0)
+        if rc:
+            raise self._err(rc, "set_graphs")
+
+    def graph_stats(self):
+        b, r = C.c_uint64(), C.c_uint64()
+        lib().hiz_graph_stats(self._h, C.byref(b), C.byref(r))
+        return int(b.value), int(r.value)
+
+    # -- torch-facing batches --
+    def compress_batch(self, fields, modes="rel", ebs=1e-3, params=None, stream=None):
+        """Compress a list of 3-D float32 CUDA tensors in one batch; returns a list of
+        uint8 tensor views (raises on the first failing field)."""
+        import torch
+        n = len(fields)
+        if isinstance(modes, (str, int)):
+            modes = [modes] * n
+        if isinstance(ebs, (float, int)):
+            ebs = [ebs] * n
+        fields = [f.contiguous() for f in fields]
+        for f in fields:
+            if f.dtype != torch.float32 or f.dim() != 3 or not f.is_cuda:
+                raise ValueError("compress_batch needs 3-D float32 tensors on a HIP device")
+        outs = [torch.empty(min(compress_bound(f.shape), 5 * f.numel() + (1 << 16)),
+                            dtype=torch.uint8, device=f.device) for f in fields]
+        sh = _stream_handle(stream)
+        sizes, st = self.compress_batch_ptr([f.data_ptr() for f in fields],
+                                            [f.shape for f in fields], modes, ebs,
+                                            [o.data_ptr() for o in outs],
+                                            [o.numel() for o in outs], params, sh)
+        for i, s_ in enumerate(st):
+            if s_ == ERR_BUFSZ:
+                outs[i] = torch.empty(sizes[i], dtype=torch.uint8, device=fields[i].device)
+                sizes[i] = self.compress_ptr(fields[i].data_ptr(), fields[i].shape, modes[i],
+                                             ebs[i], outs[i].data_ptr(), outs[i].numel(),
+                                             params, sh)
+            elif s_:
+                raise HizError(s_, f"compress_batch field {i}: "
+                               + lib().hiz_last_error(self._h).decode(errors="replace"))
+        return [o[:sz] for o, sz in zip(outs, sizes)]
+
+    def decompress_batch(self, streams, stream=None):
+        """Decompress a list of uint8 CUDA tensors in one batch; returns float32 tensors."""
+        import torch
+        streams = [s_.contiguous() for s_ in streams]
+        shapes = [inspect(s_[:512].cpu().numpy().tobytes())["dims"] for s_ in streams]
+        outs = [torch.empty(sh_, dtype=torch.float32, device=s_.device)
+                for sh_, s_ in zip(shapes, streams)]
+        dims, st = self.decompress_batch_ptr([s_.data_ptr() for s_ in streams],
+                                             [s_.numel() for s_ in streams],
+                                             [o.data_ptr() for o in outs],
+                                             [o.numel() for o in outs], _stream_handle(stream))
+        for i, s_ in enumerate(st):
+            if s_:
+                raise HizError(s_, f"decompress_batch field {i}: "
+                               + lib().hiz_last_error(self._h).decode(errors="replace"))
+        return outs
 
     # -- profiling --
     def set_profiling(self, on: bool):
