@@ -12,7 +12,15 @@ measured with HIP events on the launch stream inside the timed region.
 The CPU baseline is the oracle (single-threaded C) on a bounded slab of the
 same field.
 
+With --workload batch64 it measures instead the batch of 64 uneven fields
+(sides uniform in 32..384, spectra k^-2..k^-4, rel eb 1e-3, fieldgen.batch_specs):
+one step compresses and decompresses all 64 fields, either as 64 plain
+per-field calls (each synchronizing), as one batched call per direction, or as
+one batched call replayed from a HIP graph; `value` is the graph-replayed
+batched rate and the other two are reported beside it.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eb 1e-3]
+                       [--workload turb512|batch64]
 """
 from __future__ import annotations
 
@@ -77,12 +85,19 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--cpu-planes", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["turb512", "batch64"], default="turb512")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run 3 plain device copies of this many MiB: the reference "
+                         "kernel of known traffic that scales FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the compressor's data-parallel path runs on a "
               "single device here (multi-GPU sharding is described in DESIGN.md, not run)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        return bench_batch(args)
 
     import torch
 
@@ -105,6 +120,13 @@ def main():
     ybuf = torch.empty(shape, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
     sh = hiz.C.c_void_p(stream.cuda_stream)
+    if args.copy_mib:
+        src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         size = ctx.compress_ptr(xd.data_ptr(), shape, "rel", args.eb, zbuf.data_ptr(), cap,
@@ -206,6 +228,117 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_planes} planes")
         res["cpu_baseline"] = cpu_baseline(x, args.eb, args.cpu_planes)
+    print(json.dumps(res), flush=True)
+
+
+def bench_batch(args):
+    """64 uneven fields: plain per-field calls vs one batched call (eager / graph)."""
+    import torch
+
+    import fieldgen
+    from paper_2507_11165_amd import hiz
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    specs = fieldgen.batch_specs()
+    log(f"generating {len(specs)} fields")
+    t = time.time()
+    xs = [fieldgen.grf(sh, beta, seed) for sh, beta, seed in specs]
+    log(f"  generated in {time.time() - t:.1f}s")
+    n = len(xs)
+    Ns = [x.size for x in xs]
+    total = sum(Ns)
+    fields = [torch.from_numpy(x).to(dev) for x in xs]
+    caps = [2 * N + (1 << 20) for N in Ns]
+    outs = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    ys = [torch.empty(x.shape, dtype=torch.float32, device=dev) for x in xs]
+    ctx = hiz.Context(0)
+    sh = hiz.C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    fptr = [f.data_ptr() for f in fields]
+    optr = [o.data_ptr() for o in outs]
+    yptr = [y.data_ptr() for y in ys]
+    shapes = [x.shape for x in xs]
+    modes = ["rel"] * n
+    ebs = [args.eb] * n
+    sizes = [0] * n
+
+    def plain_step():
+        for i in range(n):
+            sizes[i] = ctx.compress_ptr(fptr[i], shapes[i], "rel", args.eb, optr[i], caps[i],
+                                        None, sh)
+        for i in range(n):
+            ctx.decompress_ptr(optr[i], sizes[i], yptr[i], Ns[i], sh)
+
+    def batch_step():
+        sz, st = ctx.compress_batch_ptr(fptr, shapes, modes, ebs, optr, caps, None, sh)
+        if any(st):
+            raise SystemExit(f"batched compression failed: {st}")
+        sizes[:] = sz
+        _, st = ctx.decompress_batch_ptr(optr, sizes, yptr, Ns, sh)
+        if any(st):
+            raise SystemExit(f"batched decompression failed: {st}")
+
+    def timed(step, graphs):
+        ctx.set_graphs(graphs)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    log("plain per-field calls")
+    t_plain = timed(plain_step, False)
+    plain_sizes = list(sizes)
+    log("batched, eager")
+    t_eager = timed(batch_step, False)
+    if sizes != plain_sizes:
+        raise SystemExit("batched stream sizes differ from per-field calls")
+    log("batched, graph replay")
+    t_graph = timed(batch_step, True)
+    builds, replays = ctx.graph_stats()
+    ctx.set_graphs(False)
+    # the bound on every element of every field
+    worst = 0.0
+    for i in range(n):
+        info = hiz.inspect(outs[i][:512].cpu().numpy().tobytes())
+        err = float((fields[i].double() - ys[i].double()).abs().max())
+        worst = max(worst, err / info["eps"])
+    if worst > 1.0:
+        raise SystemExit(f"error bound violated: max |err|/eps = {worst}")
+    gbs = lambda sec: round(8.0 * total / sec / 1e9, 2)
+    res = {
+        "metric": "compress+decompress GB/s & % HBM peak at eb=1e-3; ratio; batched vs plain",
+        "value": gbs(t_graph),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_graph * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch of 64 FP32 fields, sides uniform 32..384, GRF k^-2..k^-4, "
+                        "rel eb 1e-3; batched + HIP graph vs 64 plain per-field calls",
+            "fields": n, "points": total, "eb_mode": "rel", "eb": args.eb,
+        },
+        "plain_GBps": gbs(t_plain),
+        "batched_eager_GBps": gbs(t_eager),
+        "batched_graph_GBps": gbs(t_graph),
+        "speedup_vs_plain": round(t_plain / t_graph, 3),
+        "ms_plain": round(t_plain * 1e3, 3),
+        "ms_batched_eager": round(t_eager * 1e3, 3),
+        "ms_batched_graph": round(t_graph * 1e3, 3),
+        "graph_builds": builds, "graph_replays": replays,
+        "ratio": round(4.0 * total / sum(sizes), 4),
+        "max_err_over_eps": round(worst, 6),
+        "effective_hbm_frac": round(gbs(t_graph) / HBM_PEAK_GBS, 4),
+    }
     print(json.dumps(res), flush=True)
 
 

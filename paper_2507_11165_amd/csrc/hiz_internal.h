@@ -127,7 +127,8 @@ struct JobList {
 struct Counters {
     uint32_t enc_next;
     uint32_t dec_next;
-    uint32_t pad[14];
+    uint32_t tile_next[8]; // per XCD: tiles claimed by predict / reconstruct
+    uint32_t pad[6];
 };
 
 // ---- kernel launchers (each defined next to its kernel) ----
@@ -141,7 +142,7 @@ void launch_eps(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_tune(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s);
 void launch_tune_pick(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_predict(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
-                    hipStream_t s);
+                    Counters *cnt, hipStream_t s);
 int predict_blocks_per_cu(int tile_z);
 void launch_codebook(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_encode(const Job *d_jobs, int njobs, uint64_t total_chunks, uint64_t total_groups,
@@ -156,11 +157,61 @@ void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_decode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, hipStream_t s);
 void launch_scatter(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s);
 void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
-                        hipStream_t s);
+                        Counters *cnt, hipStream_t s);
 int reconstruct_blocks_per_cu(int tile_z);
 
 // ---- device helpers shared by the kernels ----
 #ifdef __HIPCC__
+// Pointers read from a Job are generic; cast to the global address space the
+// kernels' loads and stores compile to global instructions, whose completion
+// is counted apart from LDS operations (a generic access is also counted with
+// LDS traffic, so every LDS wait would wait for it too).
+#define HIZ_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ HIZ_GLOBAL T *gmem(T *p)
+{
+    return (HIZ_GLOBAL T *)p;
+}
+// 8- and 16-byte global accesses through the compiler's own vector types (the
+// HIP vector structs only work in the generic address space).
+typedef float hiz_f4v __attribute__((ext_vector_type(4)));
+typedef uint32_t hiz_u4v __attribute__((ext_vector_type(4)));
+typedef uint32_t hiz_u2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 gload_f4(HIZ_GLOBAL const float *p)
+{
+    const hiz_f4v v = *(HIZ_GLOBAL const hiz_f4v *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint4 gload_u4(HIZ_GLOBAL const uint8_t *p)
+{
+    const hiz_u4v v = *(HIZ_GLOBAL const hiz_u4v *)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore_f4(HIZ_GLOBAL float *p, const float4 &v)
+{
+    hiz_f4v w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *(HIZ_GLOBAL hiz_f4v *)p = w;
+}
+__device__ __forceinline__ void gstore_u4(HIZ_GLOBAL uint8_t *p, const uint4 &v)
+{
+    hiz_u4v w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *(HIZ_GLOBAL hiz_u4v *)p = w;
+}
+__device__ __forceinline__ void gstore_u2(HIZ_GLOBAL uint2 *p, const uint2 &v)
+{
+    hiz_u2v w;
+    w.x = v.x;
+    w.y = v.y;
+    *(HIZ_GLOBAL hiz_u2v *)p = w;
+}
+
 // Unit u of a launch's work list -> job index (binary search over prefixes).
 template <WorkKind K>
 __device__ inline uint64_t job_begin(const Job &j)

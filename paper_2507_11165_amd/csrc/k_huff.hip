@@ -382,7 +382,7 @@ constexpr int kEncBuf = kEncSeg + 2; // words of a wave's LDS pack buffer
 constexpr int kEncWaves = 4;
 constexpr int kGroupChunks = kEncGroupChunks;
 
-__device__ inline void load_lane_codes(const uint8_t *__restrict__ src, int P, int n,
+__device__ inline void load_lane_codes(HIZ_GLOBAL const uint8_t *__restrict__ src, int P, int n,
                                        uint32_t r[4])
 {
     // P consecutive codes (P <= 16) starting at src; n = how many are valid
@@ -391,7 +391,7 @@ __device__ inline void load_lane_codes(const uint8_t *__restrict__ src, int P, i
 #pragma unroll
         for (int k = 0; k < 4; k++)
             if (k < P / 4)
-                r[k] = reinterpret_cast<const uint32_t *>(src)[k];
+                r[k] = reinterpret_cast<HIZ_GLOBAL const uint32_t *>(src)[k];
     } else {
 #pragma unroll
         for (int k = 0; k < 16; k++)
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
             const int P = (sl + 63) / 64;
             const int n = max(0, min(P, sl - lane * P));
             uint32_t r[4], b, z;
-            load_lane_codes(J.codes + c0 + sg * kEncSeg + lane * P, P, n, r);
+            load_lane_codes(gmem(J.codes) + c0 + sg * kEncSeg + lane * P, P, n, r);
             lane_sizes(r, n, len, b, z);
             bits += b;
             zeros += z;
@@ -484,10 +484,10 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
     const uint64_t cap = J.cap;
     if (lane < nc) {
         const uint64_t ck = cfirst + lane;
-        J.woff[ck] = wbase + wi - w;
-        J.zoff[ck] = zbase + zi - z;
+        gmem(J.woff)[ck] = wbase + wi - w;
+        gmem(J.zoff)[ck] = zbase + zi - z;
         if (kOffChunks + 4 * (ck + 1) <= cap)
-            reinterpret_cast<uint32_t *>(J.stream + kOffChunks)[ck] = (uint32_t)w;
+            reinterpret_cast<HIZ_GLOBAL uint32_t *>(gmem(J.stream) + kOffChunks)[ck] = (uint32_t)w;
     }
     if (lane == 0 && cfirst + nc == J.n_chunks) {
         const uint64_t pw = wbase + gw;
@@ -536,11 +536,13 @@ __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, 
         const uint64_t ck = id - J.chunk_begin;
         const uint64_t c0 = ck << J.log2_chunk;
         const int clen = (int)(min(c0 + J.chunk, J.N) - c0);
-        const uint8_t *src = J.codes + c0;
-        const uint64_t wbase = J.woff[ck];
-        uint64_t zpos0 = J.zoff[ck];
+        HIZ_GLOBAL const uint8_t *src = gmem(J.codes) + c0;
+        HIZ_GLOBAL uint8_t *stream = gmem(J.stream);
+        HIZ_GLOBAL const float *field = gmem(J.field);
+        const uint64_t wbase = gmem(J.woff)[ck];
+        uint64_t zpos0 = gmem(J.zoff)[ck];
         const uint64_t cap = J.cap;
-        uint32_t *payload = reinterpret_cast<uint32_t *>(J.stream + st->off_payload);
+        HIZ_GLOBAL uint32_t *payload = reinterpret_cast<HIZ_GLOBAL uint32_t *>(stream + st->off_payload);
         const uint64_t pay_words_cap = cap > st->off_payload ? (cap - st->off_payload) / 4 : 0;
         const uint64_t o_idx = st->off_oidx, o_val = st->off_oval;
         const int ib = J.idx_bytes;
@@ -588,12 +590,12 @@ __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, 
                     const uint64_t gi = gfirst + k;
                     if (o_idx + (zpos + 1) * ib <= cap) {
                         if (ib == 4)
-                            reinterpret_cast<uint32_t *>(J.stream + o_idx)[zpos] = (uint32_t)gi;
+                            reinterpret_cast<HIZ_GLOBAL uint32_t *>(stream + o_idx)[zpos] = (uint32_t)gi;
                         else
-                            reinterpret_cast<uint64_t *>(J.stream + o_idx)[zpos] = gi;
+                            reinterpret_cast<HIZ_GLOBAL uint64_t *>(stream + o_idx)[zpos] = gi;
                     }
                     if (o_val + (zpos + 1) * 4 <= cap)
-                        reinterpret_cast<float *>(J.stream + o_val)[zpos] = J.field[gi];
+                        reinterpret_cast<HIZ_GLOBAL float *>(stream + o_val)[zpos] = field[gi];
                     zpos++;
                 }
             }
@@ -701,7 +703,7 @@ __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs
     __shared__ uint32_t first[kMaxCodeLen + 2];
     __shared__ uint32_t index[kMaxCodeLen + 2];
     const int t = threadIdx.x;
-    len[t] = J.stream[kOffLen + t];
+    len[t] = gmem(J.stream)[kOffLen + t];
     if (t < kMaxCodeLen + 2)
         blc[t] = 0;
     for (int i = t; i < (1 << kLutBits); i += 256)
@@ -787,7 +789,8 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         s_maxlen = dt->maxlen;
     const uint64_t lb = id - J.dblk_begin;
     const uint64_t chunk = lb * kDecChunks + t;
-    const uint32_t *counts = reinterpret_cast<const uint32_t *>(J.stream + kOffChunks);
+    HIZ_GLOBAL const uint32_t *counts =
+        reinterpret_cast<HIZ_GLOBAL const uint32_t *>(gmem(J.stream) + kOffChunks);
     // a chunk of C symbols never needs more than C words (32-bit codewords)
     uint64_t wc = chunk < J.n_chunks ? counts[chunk] : 0;
     if (wc > J.chunk) {
@@ -820,7 +823,9 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     }
     if (chunk == J.n_chunks - 1 && start + wc != pw)
         atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
-    const uint32_t *words = reinterpret_cast<const uint32_t *>(J.stream + J.off_payload);
+    HIZ_GLOBAL const uint32_t *words =
+        reinterpret_cast<HIZ_GLOBAL const uint32_t *>(gmem(J.stream) + J.off_payload);
+    HIZ_GLOBAL uint8_t *codes = gmem(J.codes);
     const uint64_t i0 = chunk << J.log2_chunk, i1 = min(i0 + J.chunk, J.N);
     const uint32_t maxlen = s_maxlen;
     const uint64_t wend = start + wc;
@@ -878,13 +883,13 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         zeros += (sym == 0);
         pack |= sym << (8 * (i & 3));
         if ((i & 3) == 3) {
-            *reinterpret_cast<uint32_t *>(J.codes + i - 3) = pack;
+            *reinterpret_cast<HIZ_GLOBAL uint32_t *>(codes + i - 3) = pack;
             pack = 0;
         }
     }
     if (!bad && (i1 & 3)) {
         for (uint64_t k = i1 & ~uint64_t(3); k < i1; k++)
-            J.codes[k] = (uint8_t)(pack >> (8 * (k & 3)));
+            codes[k] = (uint8_t)(pack >> (8 * (k & 3)));
     }
     if (bad || (used + 31) / 32 != wc)
         atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
@@ -908,22 +913,22 @@ __global__ __launch_bounds__(256) void k_scatter(const Job *__restrict__ jobs, i
     for (uint64_t u = blockIdx.x * 256ull + threadIdx.x; u < total; u += 256ull * gridDim.x) {
         const Job &J = jobs[find_job<WK_OUT>(jobs, njobs, u)];
         const uint64_t i = u - J.out_begin;
-        const uint8_t *ip = J.stream + J.off_oidx;
+        HIZ_GLOBAL const uint8_t *ip = gmem(J.stream) + J.off_oidx;
         uint64_t idx, prev = 0;
         if (J.idx_bytes == 4) {
-            idx = reinterpret_cast<const uint32_t *>(ip)[i];
+            idx = reinterpret_cast<HIZ_GLOBAL const uint32_t *>(ip)[i];
             if (i)
-                prev = reinterpret_cast<const uint32_t *>(ip)[i - 1];
+                prev = reinterpret_cast<HIZ_GLOBAL const uint32_t *>(ip)[i - 1];
         } else {
-            idx = reinterpret_cast<const uint64_t *>(ip)[i];
+            idx = reinterpret_cast<HIZ_GLOBAL const uint64_t *>(ip)[i];
             if (i)
-                prev = reinterpret_cast<const uint64_t *>(ip)[i - 1];
+                prev = reinterpret_cast<HIZ_GLOBAL const uint64_t *>(ip)[i - 1];
         }
         if (idx >= J.N || (i && prev >= idx)) {
             atomicOr(&J.st->flags, (uint32_t)ST_CORRUPT);
             continue;
         }
-        J.out[idx] = reinterpret_cast<const float *>(J.stream + J.off_oval)[i];
+        gmem(J.out)[idx] = reinterpret_cast<HIZ_GLOBAL const float *>(gmem(J.stream) + J.off_oval)[i];
     }
 }
 

@@ -149,33 +149,53 @@ __device__ __forceinline__ uint8_t quantize(float xv, float p, const QParams &q,
 // 1-D stencil across the line direction at LDS index li along an axis of
 // stride st, for a target whose coordinate on that axis is `c` in a block
 // spanning [lo, hi] on that axis (run-time presence; branch-free).
-template <bool CUB, bool FULL>
-__device__ __forceinline__ float cross_stencil(const float *__restrict__ v, int li, int st, int c,
-                                               int lo, int hi, int S, int &rank)
+// Samples of a cross-axis stencil: the presence of the samples depends only on
+// the target's coordinate on that axis, which is the same for every target of
+// a line, so the flags are fixed per line and the loads can be issued early.
+struct CrossSamples {
+    float a, b, c, d;
+};
+struct CrossFlags {
+    bool pa, pc, pd;
+};
+template <bool FULL>
+__device__ __forceinline__ CrossFlags cross_flags(int c, int lo, int hi, int S)
 {
-    const bool pa = c - 3 * S >= lo, pc = FULL || c + S <= hi, pd = c + 3 * S <= hi;
-    const float b = v[li - S * st];
-    const float a = v[pa ? li - 3 * S * st : li - S * st];
-    const int ic = pc ? li + S * st : li - S * st;
-    const float cc = v[ic];
-    const float d = v[pd ? li + 3 * S * st : ic];
+    return CrossFlags{c - 3 * S >= lo, FULL || c + S <= hi, c + 3 * S <= hi};
+}
+__device__ __forceinline__ CrossSamples cross_load(const float *__restrict__ v, int li, int st,
+                                                   int S, const CrossFlags &f)
+{
+    CrossSamples r;
+    r.b = v[li - S * st];
+    r.a = v[f.pa ? li - 3 * S * st : li - S * st];
+    const int ic = f.pc ? li + S * st : li - S * st;
+    r.c = v[ic];
+    r.d = v[f.pd ? li + 3 * S * st : ic];
+    return r;
+}
+// 1-D stencil across the line direction from its samples (missing samples
+// are never selected).
+template <bool CUB, bool FULL>
+__device__ __forceinline__ float cross_eval(const CrossSamples &s, const CrossFlags &f, int &rank)
+{
     if constexpr (FULL) {
         // inside a full block a target always has its +s neighbour
-        const float vl = (b + cc) * 0.5f;
+        const float vl = (s.b + s.c) * 0.5f;
         if constexpr (CUB) {
-            const float vc = ((b + cc) * 9.0f - (a + d)) * 0.0625f;
-            const float vqr = ((b * 3.0f + cc * 6.0f) - d) * 0.125f;
-            const float vql = ((b * 6.0f + cc * 3.0f) - a) * 0.125f;
-            const float v1 = pa ? vql : vl;
-            const float v2 = pa ? vc : vqr;
-            rank = pd ? (pa ? 4 : 3) : (pa ? 3 : 2);
-            return pd ? v2 : v1;
+            const float vc = ((s.b + s.c) * 9.0f - (s.a + s.d)) * 0.0625f;
+            const float vqr = ((s.b * 3.0f + s.c * 6.0f) - s.d) * 0.125f;
+            const float vql = ((s.b * 6.0f + s.c * 3.0f) - s.a) * 0.125f;
+            const float v1 = f.pa ? vql : vl;
+            const float v2 = f.pa ? vc : vqr;
+            rank = f.pd ? (f.pa ? 4 : 3) : (f.pa ? 3 : 2);
+            return f.pd ? v2 : v1;
         } else {
             rank = 2;
             return vl;
         }
     } else {
-        return stencil_rt<CUB>(a, b, cc, d, pa, pc, pd, rank);
+        return stencil_rt<CUB>(s.a, s.b, s.c, s.d, f.pa, f.pc, f.pd, rank);
     }
 }
 
@@ -214,16 +234,45 @@ __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restri
     } else {
         hiC = g.ey - 1;
     }
+    const CrossFlags fB = cross_flags<FULL>(cB, 0, hiB, S);
+    const CrossFlags fC = cross_flags<FULL>(cC, loC, hiC, S);
     float a = 0.f;
     float b = v[li0];
     float c = v[li0 + min(2 * S, last) * stA];
     float d = v[li0 + min(4 * S, last) * stA];
+    // loads of the first target; every later target's loads are issued one
+    // iteration ahead, so LDS latency overlaps the previous target's work
+    int lin = li0 + min(S, last) * stA;
+    float xn = 0.f;
+    uint8_t cn = 0;
+    if constexpr (COMP)
+        xn = v[lin];
+    else
+        cn = cl[lin];
+    CrossSamples sB{}, sC{};
+    if constexpr (MB)
+        sB = cross_load(v, lin, stB, S, fB);
+    if constexpr (MC)
+        sC = cross_load(v, lin, stC, S, fC);
 #pragma unroll 1
     for (int k = 0; k < K; k++) {
         const int tpos = (2 * k + 1) * S;
         if (!FULL && tpos > last)
             break;
-        const int li = li0 + tpos * stA;
+        const int li = lin;
+        const float xv = xn;
+        const uint8_t cc = cn;
+        const CrossSamples tB = sB, tC = sC;
+        // next target's loads (in bounds even past the line's end)
+        lin = li0 + min(tpos + 2 * S, last) * stA;
+        if constexpr (COMP)
+            xn = v[lin];
+        else
+            cn = cl[lin];
+        if constexpr (MB)
+            sB = cross_load(v, lin, stB, S, fB);
+        if constexpr (MC)
+            sC = cross_load(v, lin, stC, S, fC);
         const bool pa = k > 0, pc = FULL || (2 * k + 2) * S <= last,
                    pd = (2 * k + 4) * S <= last;
         int rA;
@@ -241,9 +290,9 @@ __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restri
             float pB = 0.f, pC = 0.f;
             int rB = -1, rC = -1;
             if constexpr (MB)
-                pB = cross_stencil<CUB, FULL>(v, li, stB, cB, 0, hiB, S, rB);
+                pB = cross_eval<CUB, FULL>(tB, fB, rB);
             if constexpr (MC)
-                pC = cross_stencil<CUB, FULL>(v, li, stC, cC, loC, hiC, S, rC);
+                pC = cross_eval<CUB, FULL>(tC, fC, rC);
             const float px = A == 0 ? pA : pB;
             const int rx = A == 0 ? rA : rB;
             const float py = A == 1 ? pA : (B == 1 ? pB : pC);
@@ -262,12 +311,11 @@ __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restri
         const int z = A == 2 ? z0 + tpos : z0;
         if constexpr (COMP) {
             float xo;
-            const uint8_t code = quantize(v[li], p, q, xo);
+            const uint8_t code = quantize(xv, p, q, xo);
             v[li] = xo;
             const bool own = x < g.ownx && y < g.owny && z < g.ownz;
             cb[own ? (x * 16 + y) * TS::OZ + z : TS::NC] = code;
         } else {
-            const uint8_t cc = cl[li];
             if (cc != 0)
                 v[li] = p + ((float)((int)cc - 128) * q.two_eb);
             // code 0: the exact outlier value is already in place
@@ -378,6 +426,142 @@ __device__ __forceinline__ void run_line(const LineGroup &G, int l, int S, float
     }
 }
 
+// The finest level (stride 1) inside a full tile, where 7 of every 8 targets
+// sit: the line has its full 17 points, so the eight targets, their window
+// of nine knowns and the presence of every line sample are fixed at compile
+// time. All samples are read up front at constant offsets from the line's
+// start and the eight targets run unrolled; only the cross-axis sample
+// presence (fixed per line) is a run-time choice. Arithmetic is the same as
+// in do_line, operation for operation.
+template <int TZ, int A, int MB, int MC, bool CUB, bool COMP>
+__device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__restrict__ cb,
+                                           const uint8_t *__restrict__ cl, const Geo &g, int x0,
+                                           int y0, int z0, const QParams &q)
+{
+    using TS = TileShape<TZ>;
+    constexpr int B = (A == 0) ? 1 : 0;
+    constexpr int C = (A == 2) ? 1 : 2;
+    constexpr int stA = A == 0 ? TS::PX : (A == 1 ? TS::PZ : 1);
+    constexpr int stB = B == 0 ? TS::PX : TS::PZ;
+    constexpr int stC = C == 1 ? TS::PZ : 1;
+    constexpr int M = (1 << A) | (MB << B) | (MC << C);
+    const int li0 = x0 * TS::PX + y0 * TS::PZ + z0;
+    const float *vl = v + li0;
+    // cross-axis sample presence, fixed along the line
+    const int cB = B == 0 ? x0 : y0;
+    const int cC = C == 1 ? y0 : z0;
+    const int loC = C == 2 ? (cC & ~15) : 0;
+    const CrossFlags fB = cross_flags<true>(cB, 0, kSide - 1, 1);
+    const CrossFlags fC = cross_flags<true>(cC, loC, loC + 16, 1);
+    const int oBa = fB.pa ? -3 * stB : -stB, oBd = fB.pd ? 3 * stB : stB;
+    const int oCa = fC.pa ? -3 * stC : -stC, oCd = fC.pd ? 3 * stC : stC;
+    // codes: owned lines write at a fixed step, others to the dummy slot
+    constexpr int cstep = A == 0 ? 16 * TS::OZ : (A == 1 ? TS::OZ : 1);
+    bool own;
+    int cbase;
+    if constexpr (A == 2) {
+        own = x0 < g.ownx && y0 < g.owny;
+        cbase = (x0 * 16 + y0) * TS::OZ + z0;
+    } else if constexpr (A == 1) {
+        own = x0 < g.ownx && z0 < g.ownz;
+        cbase = x0 * 16 * TS::OZ + z0;
+    } else {
+        own = y0 < g.owny && z0 < g.ownz;
+        cbase = y0 * TS::OZ + z0;
+    }
+    const int cb0 = own ? cbase : TS::NC;
+    const int cst = own ? cstep : 0;
+    float w[9];
+#pragma unroll
+    for (int j = 0; j < 9; j++)
+        w[j] = vl[2 * j * stA];
+    float xv[8];
+    uint8_t cc[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        xv[k] = vl[(2 * k + 1) * stA];
+        if constexpr (!COMP)
+            cc[k] = cl[li0 + (2 * k + 1) * stA];
+    }
+    static_for<0, 8>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int tpos = 2 * k + 1;
+        const int li = li0 + tpos * stA;
+        int rA;
+        const float pA = stencil_ct<CUB, (k > 0), true, (k < 7)>(
+            k > 0 ? w[k > 0 ? k - 1 : 0] : 0.f, w[k], w[k + 1], k < 7 ? w[k < 7 ? k + 2 : 8] : 0.f,
+            rA);
+        float p;
+        if constexpr (M == (1 << A)) {
+            p = pA;
+        } else {
+            float pB = 0.f, pC = 0.f;
+            int rB = -1, rC = -1;
+            if constexpr (MB) {
+                CrossSamples sm;
+                sm.b = v[li - stB];
+                sm.a = v[li + oBa];
+                sm.c = v[li + stB];
+                sm.d = v[li + oBd];
+                pB = cross_eval<CUB, true>(sm, fB, rB);
+            }
+            if constexpr (MC) {
+                CrossSamples sm;
+                sm.b = v[li - stC];
+                sm.a = v[li + oCa];
+                sm.c = v[li + stC];
+                sm.d = v[li + oCd];
+                pC = cross_eval<CUB, true>(sm, fC, rC);
+            }
+            const float px = A == 0 ? pA : pB;
+            const int rx = A == 0 ? rA : rB;
+            const float py = A == 1 ? pA : (B == 1 ? pB : pC);
+            const int ry = A == 1 ? rA : (B == 1 ? rB : rC);
+            const float pz = A == 2 ? pA : pC;
+            const int rz = A == 2 ? rA : rC;
+            p = md_combine<M>(px, py, pz, rx, ry, rz);
+        }
+        if constexpr (COMP) {
+            float xo;
+            const uint8_t code = quantize(xv[k], p, q, xo);
+            v[li] = xo;
+            cb[cb0 + tpos * cst] = code;
+        } else {
+            // code 0: the exact outlier value already in place is kept
+            const uint8_t c8 = cc[k];
+            v[li] = c8 != 0 ? p + ((float)((int)c8 - 128) * q.two_eb) : xv[k];
+        }
+    });
+}
+
+template <int TZ, bool CUB, bool COMP>
+__device__ __forceinline__ void run_line_s1(const LineGroup &G, int l, float *v, uint8_t *cb,
+                                            const uint8_t *cl, const Geo &g, const QParams &q)
+{
+    const uint32_t nbc = (uint32_t)(G.cntB * G.cntC);
+    const uint32_t cell = qdiv((uint32_t)l, nbc, G.mBC);
+    const uint32_t rem = (uint32_t)l - cell * nbc;
+    const uint32_t iB = qdiv(rem, (uint32_t)G.cntC, G.mC);
+    const uint32_t iC = rem - iB * (uint32_t)G.cntC;
+    const int cB = mode_coord(G.modeB, (int)iB, 1);
+    const int cC = mode_coord(G.modeC, (int)iC, 1);
+    if (G.A == 2) {
+        const int z0 = 16 * (int)cell;
+        switch (G.kind) {
+        case 0: do_line_s1<TZ, 2, 0, 0, CUB, COMP>(v, cb, cl, g, cB, cC, z0, q); break;
+        case 4: do_line_s1<TZ, 2, 1, 0, CUB, COMP>(v, cb, cl, g, cB, cC, z0, q); break;
+        case 5: do_line_s1<TZ, 2, 0, 1, CUB, COMP>(v, cb, cl, g, cB, cC, z0, q); break;
+        default: do_line_s1<TZ, 2, 1, 1, CUB, COMP>(v, cb, cl, g, cB, cC, z0, q); break;
+        }
+    } else if (G.A == 1) {
+        do_line_s1<TZ, 1, 0, 0, CUB, COMP>(v, cb, cl, g, cB, 0, cC, q);
+    } else if (G.kind == 3) {
+        do_line_s1<TZ, 0, 1, 0, CUB, COMP>(v, cb, cl, g, 0, cB, cC, q);
+    } else {
+        do_line_s1<TZ, 0, 0, 0, CUB, COMP>(v, cb, cl, g, 0, cB, cC, q);
+    }
+}
+
 // One level (stride S) in three sub-steps, each a set of line groups swept in
 // parallel by the workgroup, with a barrier between sub-steps.
 // MD: 1-D, then 2-D, then 3-D targets. SEQ(order): pass j interpolates along
@@ -428,13 +612,26 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
         const int n0 = G0.lines;
         const int n1 = n0 + (ng > 1 ? G1.lines : 0);
         const int n2 = n1 + (ng > 2 ? G2.lines : 0);
-        for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-            if (i < n0)
-                run_line<TZ, CUB, COMP, FULL>(G0, i, S, v, cb, cl, g, q);
-            else if (i < n1)
-                run_line<TZ, CUB, COMP, FULL>(G1, i - n0, S, v, cb, cl, g, q);
-            else
-                run_line<TZ, CUB, COMP, FULL>(G2, i - n1, S, v, cb, cl, g, q);
+        if (FULL && S == 1) {
+            if constexpr (FULL) {
+                for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+                    if (i < n0)
+                        run_line_s1<TZ, CUB, COMP>(G0, i, v, cb, cl, g, q);
+                    else if (i < n1)
+                        run_line_s1<TZ, CUB, COMP>(G1, i - n0, v, cb, cl, g, q);
+                    else
+                        run_line_s1<TZ, CUB, COMP>(G2, i - n1, v, cb, cl, g, q);
+                }
+            }
+        } else {
+            for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+                if (i < n0)
+                    run_line<TZ, CUB, COMP, FULL>(G0, i, S, v, cb, cl, g, q);
+                else if (i < n1)
+                    run_line<TZ, CUB, COMP, FULL>(G1, i - n0, S, v, cb, cl, g, q);
+                else
+                    run_line<TZ, CUB, COMP, FULL>(G2, i - n1, S, v, cb, cl, g, q);
+            }
         }
         __syncthreads();
     }
@@ -494,21 +691,39 @@ __device__ __forceinline__ Geo tile_geometry(const Job &J, uint64_t lt, uint64_t
     return g;
 }
 
-__device__ __forceinline__ void xcd_range(uint64_t total, uint64_t &first, uint64_t &end,
-                                          uint64_t &step)
+// Tiles handed out on demand. Each XCD (workgroups are dealt to the eight
+// XCDs round-robin by blockIdx) owns a contiguous eighth of the tile list, so
+// tiles that share halo faces meet in the same L2, and its workgroups claim
+// tiles one at a time from a counter: a workgroup that meets slower tiles
+// (partial ones at the field's faces) simply takes fewer. The claimed index
+// goes through a two-slot LDS buffer so that a claim for the next tile never
+// overwrites the one some wave is still reading.
+struct TileQueue {
+    uint64_t lo, hi;
+    uint32_t *ctr;
+};
+__device__ __forceinline__ TileQueue tile_queue(uint64_t total, Counters *cnt)
 {
-    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const uint32_t G = gridDim.x;
+    TileQueue q;
     if (G >= 8 && (G & 7) == 0) {
-        const uint32_t xcd = b & 7, l = b >> 3;
-        const uint64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
-        first = lo + l;
-        end = hi;
-        step = G >> 3;
+        const uint32_t xcd = blockIdx.x & 7;
+        q.lo = total * xcd / 8;
+        q.hi = total * (xcd + 1) / 8;
+        q.ctr = &cnt->tile_next[xcd];
     } else {
-        first = b;
-        end = total;
-        step = G;
+        q.lo = 0;
+        q.hi = total;
+        q.ctr = &cnt->tile_next[0];
     }
+    return q;
+}
+__device__ __forceinline__ uint64_t claim_tile(const TileQueue &q, uint64_t *slot, int it)
+{
+    if (threadIdx.x == 0)
+        slot[it & 1] = q.lo + atomicAdd(q.ctr, 1u);
+    __syncthreads();
+    return slot[it & 1];
 }
 
 // ---------------------------------------------------------------------------
@@ -519,7 +734,7 @@ __device__ __forceinline__ void xcd_range(uint64_t total, uint64_t &first, uint6
 // ---------------------------------------------------------------------------
 template <int TZ>
 __device__ __forceinline__ void load_tile_values(float *__restrict__ v,
-                                                 const float *__restrict__ field,
+                                                 HIZ_GLOBAL const float *__restrict__ field,
                                                  const uint64_t *rowoff, const Geo &g, bool vec,
                                                  bool track, uint32_t &kmn, uint32_t &kmx,
                                                  bool &bad)
@@ -533,31 +748,39 @@ __device__ __forceinline__ void load_tile_values(float *__restrict__ v,
             kmx = max(kmx, k);
         }
     };
+    // the thread index passes through an empty asm so that the per-piece
+    // index arithmetic is redone per tile instead of being hoisted out of the
+    // persistent tile loop into dozens of long-lived registers
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     if (vec) {
         constexpr int PIECES = 4 * TZ + 1; // 4*TZ float4 pieces and the face element
         constexpr int ITEMS = TS::NROW * PIECES;
-        constexpr int BATCH = 4;           // pieces in flight per thread
+        // every piece of a thread in flight at once (one memory round trip)
+        constexpr int BATCH = (ITEMS + 255) / 256 < 12 ? (ITEMS + 255) / 256 : 12;
 #pragma nounroll
         for (int i0 = 0; i0 < ITEMS; i0 += 256 * BATCH) {
+            // pieces and face elements land in separate registers, so no
+            // load has to complete before another branch writes its target
             float4 buf[BATCH];
+            float face[BATCH];
 #pragma unroll
             for (int k = 0; k < BATCH; k++) {
-                const int i = i0 + threadIdx.x + 256 * k;
+                const int i = i0 + tid + 256 * k;
                 const int r = i / PIECES, pc = i - r * PIECES;
                 const int y = r % kSide, x = r / kSide;
                 buf[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (i < ITEMS && x < g.ex && y < g.ey) {
-                    const float *rp = field + rowoff[r];
-                    const int z0 = 4 * pc;
-                    if (pc < 4 * TZ && z0 + 4 <= g.ez)
-                        buf[k] = *reinterpret_cast<const float4 *>(rp + z0);
-                    else if (pc == 4 * TZ && 16 * TZ < g.ez)
-                        buf[k].x = rp[16 * TZ];
-                }
+                face[k] = 0.f;
+                const bool row = i < ITEMS && x < g.ex && y < g.ey;
+                HIZ_GLOBAL const float *rp = field + rowoff[row ? r : 0];
+                if (row && pc < 4 * TZ && 4 * pc + 4 <= g.ez)
+                    buf[k] = gload_f4(rp + 4 * pc);
+                if (row && pc == 4 * TZ && 16 * TZ < g.ez)
+                    face[k] = rp[16 * TZ];
             }
 #pragma unroll
             for (int k = 0; k < BATCH; k++) {
-                const int i = i0 + threadIdx.x + 256 * k;
+                const int i = i0 + tid + 256 * k;
                 const int r = i / PIECES, pc = i - r * PIECES;
                 const int y = r % kSide, x = r / kSide;
                 if (i < ITEMS && x < g.ex && y < g.ey) {
@@ -580,8 +803,8 @@ __device__ __forceinline__ void load_tile_values(float *__restrict__ v,
                             }
                         }
                     } else if (16 * TZ < g.ez) {
-                        vp[16 * TZ] = buf[k].x;
-                        note(buf[k].x);
+                        vp[16 * TZ] = face[k];
+                        note(face[k]);
                     }
                 }
             }
@@ -593,7 +816,7 @@ __device__ __forceinline__ void load_tile_values(float *__restrict__ v,
             float b[8];
 #pragma unroll
             for (int k = 0; k < 8; k++) {
-                const int i = i0 + threadIdx.x + 256 * k;
+                const int i = i0 + tid + 256 * k;
                 const int z = i % TS::EZ, r = i / TS::EZ;
                 const int y = r % kSide, x = r / kSide;
                 b[k] = 0.f;
@@ -602,7 +825,7 @@ __device__ __forceinline__ void load_tile_values(float *__restrict__ v,
             }
 #pragma unroll
             for (int k = 0; k < 8; k++) {
-                const int i = i0 + threadIdx.x + 256 * k;
+                const int i = i0 + tid + 256 * k;
                 const int z = i % TS::EZ, r = i / TS::EZ;
                 const int y = r % kSide, x = r / kSide;
                 if (i < NE && x < g.ex && y < g.ey && z < g.ez) {
@@ -617,35 +840,37 @@ __device__ __forceinline__ void load_tile_values(float *__restrict__ v,
 // Codes of the whole tile region (with faces) into LDS.
 template <int TZ>
 __device__ __forceinline__ void load_tile_codes(uint8_t *__restrict__ cl,
-                                                const uint8_t *__restrict__ codes,
+                                                HIZ_GLOBAL const uint8_t *__restrict__ codes,
                                                 const uint64_t *rowoff, const Geo &g, bool vec)
 {
     using TS = TileShape<TZ>;
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     if (vec) {
         constexpr int PIECES = TZ + 1; // TZ 16-byte pieces and the face byte
         constexpr int ITEMS = TS::NROW * PIECES;
-        constexpr int BATCH = 2;
+        constexpr int BATCH = (ITEMS + 255) / 256 < 8 ? (ITEMS + 255) / 256 : 8;
 #pragma nounroll
         for (int i0 = 0; i0 < ITEMS; i0 += 256 * BATCH) {
             uint4 buf[BATCH];
+            uint32_t face[BATCH];
 #pragma unroll
             for (int k = 0; k < BATCH; k++) {
-                const int i = i0 + threadIdx.x + 256 * k;
+                const int i = i0 + tid + 256 * k;
                 const int r = i / PIECES, pc = i - r * PIECES;
                 const int y = r % kSide, x = r / kSide;
                 buf[k] = make_uint4(0, 0, 0, 0);
-                if (i < ITEMS && x < g.ex && y < g.ey) {
-                    const uint8_t *rp = codes + rowoff[r];
-                    const int z0 = 16 * pc;
-                    if (pc < TZ && z0 + 16 <= g.ez)
-                        buf[k] = *reinterpret_cast<const uint4 *>(rp + z0);
-                    else if (pc == TZ && z0 < g.ez)
-                        buf[k].x = rp[z0];
-                }
+                face[k] = 0;
+                const bool row = i < ITEMS && x < g.ex && y < g.ey;
+                HIZ_GLOBAL const uint8_t *rp = codes + rowoff[row ? r : 0];
+                if (row && pc < TZ && 16 * pc + 16 <= g.ez)
+                    buf[k] = gload_u4(rp + 16 * pc);
+                if (row && pc == TZ && 16 * pc < g.ez)
+                    face[k] = rp[16 * pc];
             }
 #pragma unroll
             for (int k = 0; k < BATCH; k++) {
-                const int i = i0 + threadIdx.x + 256 * k;
+                const int i = i0 + tid + 256 * k;
                 const int r = i / PIECES, pc = i - r * PIECES;
                 const int y = r % kSide, x = r / kSide;
                 if (i < ITEMS && x < g.ex && y < g.ey) {
@@ -661,7 +886,7 @@ __device__ __forceinline__ void load_tile_codes(uint8_t *__restrict__ cl,
                         for (int z = z0; z < g.ez; z++)
                             cp[z - z0] = codes[rowoff[r] + z];
                     } else if (z0 < g.ez) {
-                        cp[0] = (uint8_t)buf[k].x;
+                        cp[0] = (uint8_t)face[k];
                     }
                 }
             }
@@ -697,7 +922,7 @@ __device__ __forceinline__ void load_tile_codes(uint8_t *__restrict__ cl,
 // ---------------------------------------------------------------------------
 template <int TZ>
 __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, int njobs,
-                                                 uint64_t total)
+                                                 uint64_t total, Counters *cnt)
 {
     using TS = TileShape<TZ>;
     __shared__ float v[TS::NV];
@@ -709,12 +934,16 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
     __shared__ uint32_t skip;
     __shared__ uint32_t red[8];
 
+    __shared__ uint64_t s_tile[2];
+
     const int t = threadIdx.x;
     hist[t] = 0;
     int cur = -1;
-    uint64_t first, end, step;
-    xcd_range(total, first, end, step);
-    for (uint64_t u = first; u < end; u += step) {
+    const TileQueue tq = tile_queue(total, cnt);
+    for (int it = 0;; it++) {
+        const uint64_t u = claim_tile(tq, s_tile, it);
+        if (u >= tq.hi)
+            break;
         const int ji = find_job<WK_TILE>(jobs, njobs, u);
         const Job &J = jobs[ji];
         if (ji != cur) {
@@ -753,23 +982,25 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
         uint32_t kmn = 0xffffffffu, kmx = 0u;
         bool bad = false;
         const bool vec = (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.field) & 15) == 0;
-        load_tile_values<TZ>(v, J.field, rowoff, g, vec, abs_mode, kmn, kmx, bad);
+        load_tile_values<TZ>(v, gmem(J.field), rowoff, g, vec, abs_mode, kmn, kmx, bad);
         if (abs_mode) {
             if (__any(bad) && (t & 63) == 0)
                 atomicOr(&J.st->flags, (uint32_t)ST_NONFINITE);
             block_minmax(kmn, kmx, red);
             if (t == 0)
-                J.mm_part[u - J.tile_begin] = make_uint2(kmn, kmx);
+                gstore_u2(gmem(J.mm_part) + (u - J.tile_begin), make_uint2(kmn, kmx));
         }
-        // anchors owned by this tile: local (0, 0, 16j)
-        if (t < TZ && 16 * t < g.ownz) {
+        // anchors owned by this tile: local (0, 0, 16j), stored raw from the
+        // tile in LDS (the levels never write them)
+        if (t < TZ && 16 * t < g.ownz)
             cb[t * 16] = 128;
+        __syncthreads();
+        if (t < TZ && 16 * t < g.ownz) {
             const uint64_t ai = ((uint64_t)bx * J.nb[1] + by) * J.nb[2] + bz0 + t;
             const uint64_t off = J.off_anchors + 4 * ai;
             if (off + 4 <= J.cap)
-                *reinterpret_cast<float *>(J.stream + off) = J.field[rowoff[0] + 16 * t];
+                *reinterpret_cast<HIZ_GLOBAL float *>(gmem(J.stream) + off) = v[16 * t];
         }
-        __syncthreads();
         walk_levels<TZ, true>(v, cb, nullptr, g, cfg, qp);
         // codes of owned points -> global, histogram in LDS
         if (g.ownz == TS::OZ && (dz & 15) == 0) {
@@ -778,7 +1009,7 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
                     const uint4 c16 = *reinterpret_cast<const uint4 *>(&cb[r * TS::OZ + 16 * w]);
-                    *reinterpret_cast<uint4 *>(J.codes + rowoff[x * kSide + y] + 16 * w) = c16;
+                    gstore_u4(gmem(J.codes) + rowoff[x * kSide + y] + 16 * w, c16);
                     const uint32_t cw[4] = {c16.x, c16.y, c16.z, c16.w};
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
@@ -795,7 +1026,7 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny && z < g.ownz) {
                     const uint8_t c = cb[r * TS::OZ + z];
-                    J.codes[rowoff[x * kSide + y] + z] = c;
+                    gmem(J.codes)[rowoff[x * kSide + y] + z] = c;
                     atomicAdd(&hist[c], 1u);
                 }
             }
@@ -811,22 +1042,22 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
 }
 
 template <int TZ> static void launch_predict_t(const Job *d_jobs, int njobs, uint64_t total,
-                                              int grid, hipStream_t s)
+                                              int grid, Counters *cnt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_predict<TZ>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, total);
+    hipLaunchKernelGGL(k_predict<TZ>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, total, cnt);
 }
 
 void launch_predict(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
-                    hipStream_t s)
+                    Counters *cnt, hipStream_t s)
 {
     if (total == 0)
         return;
     if (tile_z == 1)
-        launch_predict_t<1>(d_jobs, njobs, total, grid, s);
+        launch_predict_t<1>(d_jobs, njobs, total, grid, cnt, s);
     else if (tile_z == 4)
-        launch_predict_t<4>(d_jobs, njobs, total, grid, s);
+        launch_predict_t<4>(d_jobs, njobs, total, grid, cnt, s);
     else
-        launch_predict_t<2>(d_jobs, njobs, total, grid, s);
+        launch_predict_t<2>(d_jobs, njobs, total, grid, cnt, s);
 }
 
 int predict_blocks_per_cu(int tile_z)
@@ -846,7 +1077,7 @@ int predict_blocks_per_cu(int tile_z)
 // ---------------------------------------------------------------------------
 template <int TZ>
 __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ jobs, int njobs,
-                                                     uint64_t total)
+                                                     uint64_t total, Counters *cnt)
 {
     using TS = TileShape<TZ>;
     __shared__ float v[TS::NV];
@@ -854,12 +1085,15 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
     __shared__ uint64_t rowoff[TS::NROW];
     __shared__ uint8_t cfg[kLevels][3];
     __shared__ QParams qp;
+    __shared__ uint64_t s_tile[2];
 
     const int t = threadIdx.x;
     int cur = -1;
-    uint64_t first, end, step;
-    xcd_range(total, first, end, step);
-    for (uint64_t u = first; u < end; u += step) {
+    const TileQueue tq = tile_queue(total, cnt);
+    for (int it = 0;; it++) {
+        const uint64_t u = claim_tile(tq, s_tile, it);
+        if (u >= tq.hi)
+            break;
         const int ji = find_job<WK_TILE>(jobs, njobs, u);
         const Job &J = jobs[ji];
         if (ji != cur) {
@@ -883,9 +1117,10 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
             rowoff[r] = ((ox + x) * dy + (oy + y)) * dz + oz;
         }
         __syncthreads();
-        const float *anchors = reinterpret_cast<const float *>(J.stream + J.off_anchors);
+        HIZ_GLOBAL const float *anchors =
+            reinterpret_cast<HIZ_GLOBAL const float *>(gmem(J.stream) + J.off_anchors);
         const bool vec = (dz & 15) == 0;
-        load_tile_codes<TZ>(cl, J.codes, rowoff, g, vec);
+        load_tile_codes<TZ>(cl, gmem(J.codes), rowoff, g, vec);
         // anchors of the tile region: every coordinate a multiple of 16
         if (t < 4 * (TZ + 1)) {
             const int x = 16 * (t & 1), y = 16 * ((t >> 1) & 1), z = 16 * (t >> 2);
@@ -913,7 +1148,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
                     hit[k] = i < NE && x < g.ex && y < g.ey && z < g.ez &&
                              cl[x * TS::PX + y * TS::PZ + z] == 0 &&
                              !((x & 15) == 0 && (y & 15) == 0 && (z & 15) == 0);
-                    ov[k] = hit[k] ? J.out[rowoff[r] + z] : 0.f;
+                    ov[k] = hit[k] ? gmem(J.out)[rowoff[r] + z] : 0.f;
                 }
 #pragma unroll
                 for (int k = 0; k < 8; k++) {
@@ -934,8 +1169,8 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
                     const float *vp = v + x * TS::PX + y * TS::PZ + 4 * w;
-                    *reinterpret_cast<float4 *>(J.out + rowoff[x * kSide + y] + 4 * w) =
-                        make_float4(vp[0], vp[1], vp[2], vp[3]);
+                    gstore_f4(gmem(J.out) + rowoff[x * kSide + y] + 4 * w,
+                              make_float4(vp[0], vp[1], vp[2], vp[3]));
                 }
             }
         } else {
@@ -943,7 +1178,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
                 const int z = i % TS::OZ, r = i / TS::OZ;
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny && z < g.ownz)
-                    J.out[rowoff[x * kSide + y] + z] = v[x * TS::PX + y * TS::PZ + z];
+                    gmem(J.out)[rowoff[x * kSide + y] + z] = v[x * TS::PX + y * TS::PZ + z];
             }
         }
         __syncthreads();
@@ -951,22 +1186,23 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
 }
 
 template <int TZ> static void launch_reconstruct_t(const Job *d_jobs, int njobs, uint64_t total,
-                                                  int grid, hipStream_t s)
+                                                  int grid, Counters *cnt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reconstruct<TZ>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, total);
+    hipLaunchKernelGGL(k_reconstruct<TZ>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, total,
+                       cnt);
 }
 
 void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
-                        hipStream_t s)
+                        Counters *cnt, hipStream_t s)
 {
     if (total == 0)
         return;
     if (tile_z == 1)
-        launch_reconstruct_t<1>(d_jobs, njobs, total, grid, s);
+        launch_reconstruct_t<1>(d_jobs, njobs, total, grid, cnt, s);
     else if (tile_z == 4)
-        launch_reconstruct_t<4>(d_jobs, njobs, total, grid, s);
+        launch_reconstruct_t<4>(d_jobs, njobs, total, grid, cnt, s);
     else
-        launch_reconstruct_t<2>(d_jobs, njobs, total, grid, s);
+        launch_reconstruct_t<2>(d_jobs, njobs, total, grid, cnt, s);
 }
 
 int reconstruct_blocks_per_cu(int tile_z)

@@ -76,15 +76,15 @@ __global__ __launch_bounds__(256) void k_minmax(const Job *__restrict__ jobs, in
         const uint64_t lu = u - J.mm_begin;
         const uint64_t lo = lu * kMmUnit;
         const uint64_t hi = min(lo + kMmUnit, J.N);
-        const float *f = J.field;
+        HIZ_GLOBAL const float *f = gmem(J.field);
         uint32_t kmn = 0xffffffffu, kmx = 0u;
         bool bad = false;
         const bool vec = ((reinterpret_cast<uintptr_t>(f) & 15u) == 0) && (hi - lo == kMmUnit);
         if (vec) {
-            const float4 *f4 = reinterpret_cast<const float4 *>(f + lo);
+            HIZ_GLOBAL const float *fb = f + lo;
 #pragma unroll 4
             for (int k = 0; k < (int)(kMmUnit / 4 / 256); k++) {
-                const float4 q = f4[k * 256 + t];
+                const float4 q = gload_f4(fb + 4 * (k * 256 + t));
                 float e[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_minmax(const Job *__restrict__ jobs, in
             atomicOr(&J.st->flags, (uint32_t)ST_NONFINITE);
         block_minmax(kmn, kmx, red);
         if (t == 0)
-            J.mm_part[lu] = make_uint2(kmn, kmx);
+            gstore_u2(gmem(J.mm_part) + lu, make_uint2(kmn, kmx));
     }
 }
 
@@ -337,7 +337,8 @@ __global__ __launch_bounds__(256) void k_tune(const Job *__restrict__ jobs, int 
     const uint64_t dy = J.dims[1], dz = J.dims[2];
     for (int i = threadIdx.x; i < kSide * kSide * kSide; i += blockDim.x) {
         int z = i % kSide, r = i / kSide, y = r % kSide, x = r / kSide;
-        blk[i] = J.field[((ba * kAnchor + x) * dy + (bb * kAnchor + y)) * dz + bc * kAnchor + z];
+        blk[i] = gmem(J.field)[((ba * kAnchor + x) * dy + (bb * kAnchor + y)) * dz +
+                               bc * kAnchor + z];
     }
     __syncthreads();
     const double scale = st->tune_scale;

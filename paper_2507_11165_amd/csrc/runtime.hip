@@ -677,7 +677,8 @@ void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int 
     }
     {
         Scope sc(c, s, "predict_quant", prof);
-        launch_predict(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, false), s);
+        launch_predict(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, false), L.d_cnt,
+                       s);
     }
     {
         Scope sc(c, s, "codebook", prof);
@@ -714,7 +715,8 @@ void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, in
     }
     {
         Scope sc(c, s, "reconstruct", prof);
-        launch_reconstruct(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, true), s);
+        launch_reconstruct(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, true),
+                           L.d_cnt, s);
     }
     launch_gather_results(L.d_jobs, nj, L.d_res, s);
     hipMemcpyAsync(L.h_res, L.d_res, (size_t)kResultBytes * nj, hipMemcpyDeviceToHost, s);
