@@ -99,6 +99,12 @@ const char *hiz_last_error(const hiz_ctx *ctx);
  * outlier and 32-bit codewords); 0 if dims are invalid. */
 uint64_t hiz_compress_bound(const uint64_t dims[3]);
 
+/* Device workspace one field of these dims can need inside a (batched) call,
+ * in either direction; a context created with the sum over a batch's fields
+ * (plus 1 MiB) never grows its workspace for that batch. 0 if dims are
+ * invalid. */
+uint64_t hiz_workspace_bound(const uint64_t dims[3]);
+
 /* Z = Cmp(X) (Sec. 3.1). Reads the field d_field (dims[0]*dims[1]*dims[2]
  * floats), writes the stream to d_out (capacity out_cap bytes) and its size
  * to *out_size (host memory) after synchronizing `stream`.
@@ -184,6 +190,65 @@ hiz_status hiz_batch_finish(hiz_ctx *ctx, uint64_t *sizes, uint64_t *dims,
 hiz_status hiz_set_graphs(hiz_ctx *ctx, int on);
 /* Graphs built and replays launched on this context so far. */
 void hiz_graph_stats(const hiz_ctx *ctx, uint64_t *builds, uint64_t *replays);
+
+/* ---- Serving: continuous batching of requests on one device -------------
+ * A server owns `slots` contexts (1..16), each with its own HIP stream and a
+ * workspace of an equal share of `mem_budget` bytes (0 = a quarter of the
+ * device memory free at creation), allocated up front: nothing is allocated
+ * while serving, and codebooks, decoder tables and code buffers stay on the
+ * device. A background thread forms batches: a free slot takes the oldest
+ * waiting request and, behind it in arrival order, further requests of the
+ * same kind while the batch fits the slot's workspace (admission by device
+ * memory, sized with hiz_workspace_bound) and holds at most `max_batch`
+ * requests; requests arriving while batches run are batched onto the next
+ * free slot, so batches of different slots overlap on the GPU. Each request
+ * gives the same bytes (compress) or field (decompress) as a single call.
+ * The caller owns every request buffer and keeps it valid until the
+ * request's completion has been polled. params (may be NULL) apply to every
+ * compression. Submit and poll are thread-safe. */
+typedef struct hiz_server hiz_server;
+enum { HIZ_OP_COMPRESS = 0, HIZ_OP_DECOMPRESS = 1 };
+typedef struct {
+    uint64_t id;         /* caller tag, returned in the completion */
+    int op;              /* HIZ_OP_COMPRESS or HIZ_OP_DECOMPRESS */
+    const void *d_in;    /* compress: FP32 field; decompress: stream */
+    uint64_t in_size;    /* decompress: stream bytes */
+    uint64_t dims[3];    /* compress: field dims */
+    int mode;            /* compress: hiz_eb_mode */
+    double eb;           /* compress: error bound */
+    void *d_out;         /* compress: stream buffer; decompress: field buffer */
+    uint64_t out_cap;    /* bytes (compress) or elements (decompress) */
+} hiz_request;
+typedef struct {
+    uint64_t id;
+    hiz_status status;
+    uint64_t size;       /* stream bytes (compress; needed size on BUFSZ) or elements */
+    double t_submit, t_start, t_done; /* seconds on hiz_server_clock */
+    int batch_size;      /* requests in the batch it ran in */
+    int slot;
+} hiz_completion;
+typedef struct {
+    uint64_t submitted, completed, batches;
+    int max_running;     /* most batches in flight at once */
+    int slots;
+    uint64_t slot_capacity;
+} hiz_server_stats;
+
+hiz_status hiz_server_create(int device, int slots, uint64_t mem_budget, int max_batch,
+                             const hiz_params *params, hiz_server **out);
+/* Queue one request (never blocks on the device). A request larger than a
+ * slot's workspace completes with HIZ_ERR_NOMEM. */
+hiz_status hiz_server_submit(hiz_server *srv, const hiz_request *req);
+/* Move up to `max` completions to `out`, oldest first; returns how many. */
+int hiz_server_poll(hiz_server *srv, hiz_completion *out, int max);
+/* Wait until every submitted request has completed (timeout_s <= 0: no
+ * limit); HIZ_ERR_HIP on timeout. Completions stay available to poll. */
+hiz_status hiz_server_drain(hiz_server *srv, double timeout_s);
+void hiz_server_get_stats(hiz_server *srv, hiz_server_stats *out);
+/* The monotonic clock of the completion timestamps, in seconds. */
+double hiz_server_clock(void);
+/* Finishes every submitted request, then stops the loop and frees the slots. */
+void hiz_server_destroy(hiz_server *srv);
 
 /* Per-kernel timing of the calls made on this context while profiling is on
  * (HIP events recorded on the caller's stream around each launch). */

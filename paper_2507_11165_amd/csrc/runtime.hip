@@ -1116,6 +1116,28 @@ uint64_t hiz_compress_bound(const uint64_t dims[3])
     return kOffChunks + 4 * chunks + 4 * anchors + 12 * N + 4 * (N + chunks) + 64;
 }
 
+uint64_t hiz_workspace_bound(const uint64_t dims[3])
+{
+    if (!dims)
+        return 0;
+    uint64_t N = 1;
+    for (int k = 0; k < 3; k++) {
+        if (dims[k] == 0 || dims[k] > kMaxN || N > kMaxN / dims[k])
+            return 0;
+        N *= dims[k];
+    }
+    // the largest layout either direction can take: shortest chunks, one-block
+    // tiles, and one 256-byte alignment gap per workspace section
+    const uint64_t chunks = cdiv(N, 256);
+    const uint64_t groups = cdiv(chunks, kEncGroupChunks);
+    const uint64_t tiles = cdiv(dims[0], kAnchor) * cdiv(dims[1], kAnchor) * cdiv(dims[2], kAnchor);
+    const uint64_t mm = std::max<uint64_t>(cdiv(N, 16384), tiles);
+    const uint64_t per_job = sizeof(Job) + kResultBytes + sizeof(FieldState) + 10 * 256;
+    const uint64_t comp = per_job + N + 16 * groups + 16 * chunks + 8 * mm;
+    const uint64_t dec = per_job + sizeof(DecTables) + N + 8 * cdiv(chunks, 256);
+    return std::max(comp, dec);
+}
+
 void hiz_set_profiling(hiz_ctx *c, int on)
 {
     if (c)

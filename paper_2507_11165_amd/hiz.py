@@ -21,11 +21,14 @@ _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NONFINITE", 3: "ERR_BUFSZ", 4: "ERR_CO
            5: "ERR_NOMEM", 6: "ERR_HIP"}
 
 # exported symbols (kept in step with include/hiz.h)
-SYMBOLS = ["hiz_create", "hiz_destroy", "hiz_last_error", "hiz_compress_bound", "hiz_compress",
-           "hiz_decompress", "hiz_inspect", "hiz_compress_batch", "hiz_decompress_batch",
-           "hiz_compress_batch_submit", "hiz_decompress_batch_submit", "hiz_batch_ready",
-           "hiz_batch_finish", "hiz_set_graphs", "hiz_graph_stats", "hiz_set_profiling",
-           "hiz_get_profile", "hiz_reset_profile"]
+SYMBOLS = ["hiz_create", "hiz_destroy", "hiz_last_error", "hiz_compress_bound",
+           "hiz_workspace_bound", "hiz_compress", "hiz_decompress", "hiz_inspect",
+           "hiz_compress_batch", "hiz_decompress_batch", "hiz_compress_batch_submit",
+           "hiz_decompress_batch_submit", "hiz_batch_ready", "hiz_batch_finish", "hiz_set_graphs",
+           "hiz_graph_stats", "hiz_server_create", "hiz_server_submit", "hiz_server_poll",
+           "hiz_server_drain", "hiz_server_get_stats", "hiz_server_clock", "hiz_server_destroy",
+           "hiz_set_profiling", "hiz_get_profile", "hiz_reset_profile"]
+OP_COMPRESS, OP_DECOMPRESS = 0, 1
 
 
 class Params(C.Structure):
@@ -39,6 +42,23 @@ class Info(C.Structure):
                 ("constant", C.c_int), ("level_cfg", (C.c_uint8 * 3) * 4), ("chunk", C.c_uint32),
                 ("n_outliers", C.c_uint64), ("n_chunks", C.c_uint64),
                 ("payload_words", C.c_uint64), ("total_bytes", C.c_uint64)]
+
+
+class Request(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("op", C.c_int), ("d_in", C.c_void_p), ("in_size", C.c_uint64),
+                ("dims", C.c_uint64 * 3), ("mode", C.c_int), ("eb", C.c_double),
+                ("d_out", C.c_void_p), ("out_cap", C.c_uint64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int), ("size", C.c_uint64),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("batch_size", C.c_int), ("slot", C.c_int)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("batches", C.c_uint64),
+                ("max_running", C.c_int), ("slots", C.c_int), ("slot_capacity", C.c_uint64)]
 
 
 class KernelStat(C.Structure):
@@ -96,6 +116,19 @@ def lib():
             L.hiz_set_graphs.argtypes = [C.c_void_p, C.c_int]
             L.hiz_graph_stats.argtypes = [C.c_void_p, u64p, u64p]
             L.hiz_graph_stats.restype = None
+            L.hiz_workspace_bound.argtypes = [u64p]
+            L.hiz_workspace_bound.restype = C.c_uint64
+            L.hiz_server_create.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_int,
+                                            C.POINTER(Params), C.POINTER(C.c_void_p)]
+            L.hiz_server_submit.argtypes = [C.c_void_p, C.POINTER(Request)]
+            L.hiz_server_poll.argtypes = [C.c_void_p, C.POINTER(Completion), C.c_int]
+            L.hiz_server_drain.argtypes = [C.c_void_p, C.c_double]
+            L.hiz_server_get_stats.argtypes = [C.c_void_p, C.POINTER(ServerStats)]
+            L.hiz_server_get_stats.restype = None
+            L.hiz_server_clock.argtypes = []
+            L.hiz_server_clock.restype = C.c_double
+            L.hiz_server_destroy.argtypes = [C.c_void_p]
+            L.hiz_server_destroy.restype = None
             L.hiz_set_profiling.argtypes = [C.c_void_p, C.c_int]
             L.hiz_set_profiling.restype = None
             L.hiz_get_profile.argtypes = [C.c_void_p, C.POINTER(KernelStat), C.c_int]
@@ -111,6 +144,10 @@ def _dims(shape):
 
 def compress_bound(shape) -> int:
     return int(lib().hiz_compress_bound(_dims(shape)))
+
+
+def workspace_bound(shape) -> int:
+    return int(lib().hiz_workspace_bound(_dims(shape)))
 
 
 def make_params(tune=True, level_cfg=None, chunk=0, tile_z=0) -> Params:
@@ -380,6 +417,73 @@ class Context:
         n = lib().hiz_get_profile(self._h, arr, 64)
         return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
                 for i in range(min(n, 64))}
+
+
+class Server:
+    """Continuous-batching request loop on one device (hiz_server_* of the C ABI).
+
+    Requests carry raw device pointers; the caller keeps their buffers alive until
+    the request's completion has been polled."""
+
+    def __init__(self, device=0, slots=4, mem_budget=0, max_batch=32, params=None):
+        h = C.c_void_p()
+        p = C.byref(params) if params is not None else None
+        rc = lib().hiz_server_create(int(device), int(slots), int(mem_budget), int(max_batch), p,
+                                     C.byref(h))
+        if rc:
+            raise HizError(rc, "hiz_server_create")
+        self._h = h
+
+    def submit_compress(self, rid, field_ptr, shape, mode, eb, out_ptr, out_cap):
+        r = Request(id=int(rid), op=OP_COMPRESS, d_in=field_ptr, in_size=0, mode=_mode(mode),
+                    eb=float(eb), d_out=out_ptr, out_cap=int(out_cap))
+        for k in range(3):
+            r.dims[k] = int(shape[k])
+        rc = lib().hiz_server_submit(self._h, C.byref(r))
+        if rc:
+            raise HizError(rc, "hiz_server_submit")
+
+    def submit_decompress(self, rid, stream_ptr, stream_size, out_ptr, out_elems):
+        r = Request(id=int(rid), op=OP_DECOMPRESS, d_in=stream_ptr, in_size=int(stream_size),
+                    mode=0, eb=0.0, d_out=out_ptr, out_cap=int(out_elems))
+        rc = lib().hiz_server_submit(self._h, C.byref(r))
+        if rc:
+            raise HizError(rc, "hiz_server_submit")
+
+    def poll(self, max_n=256):
+        arr = (Completion * max_n)()
+        n = lib().hiz_server_poll(self._h, arr, max_n)
+        return [{"id": arr[i].id, "status": arr[i].status, "size": arr[i].size,
+                 "t_submit": arr[i].t_submit, "t_start": arr[i].t_start,
+                 "t_done": arr[i].t_done, "batch_size": arr[i].batch_size,
+                 "slot": arr[i].slot} for i in range(n)]
+
+    def drain(self, timeout_s=0.0):
+        rc = lib().hiz_server_drain(self._h, float(timeout_s))
+        if rc:
+            raise HizError(rc, "hiz_server_drain (timeout)")
+
+    def stats(self):
+        st = ServerStats()
+        lib().hiz_server_get_stats(self._h, C.byref(st))
+        return {"submitted": st.submitted, "completed": st.completed, "batches": st.batches,
+                "max_running": st.max_running, "slots": st.slots,
+                "slot_capacity": st.slot_capacity}
+
+    @staticmethod
+    def clock():
+        return float(lib().hiz_server_clock())
+
+    def close(self):
+        if self._h:
+            lib().hiz_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _ctx = {}
