@@ -40,7 +40,7 @@ enum : uint32_t {
 };
 
 // Decoder lookup tables of one field, built once per decompression.
-constexpr int kLutBits = 11;
+constexpr int kLutBits = 13;
 struct DecTables {
     uint16_t lut[1 << kLutBits]; // (len << 8) | symbol for codes up to kLutBits bits; 0 = slow path
     uint32_t first[kMaxCodeLen + 2]; // first canonical code of each length

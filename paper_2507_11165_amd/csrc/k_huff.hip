@@ -702,12 +702,11 @@ __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs
     __shared__ uint32_t blc[kMaxCodeLen + 2];
     __shared__ uint32_t first[kMaxCodeLen + 2];
     __shared__ uint32_t index[kMaxCodeLen + 2];
+    __shared__ uint8_t s_sorted[256];
     const int t = threadIdx.x;
     len[t] = gmem(J.stream)[kOffLen + t];
     if (t < kMaxCodeLen + 2)
         blc[t] = 0;
-    for (int i = t; i < (1 << kLutBits); i += 256)
-        dt->lut[i] = 0;
     __syncthreads();
     const int L = len[t];
     if (L >= 1 && L <= kMaxCodeLen)
@@ -737,13 +736,21 @@ __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs
         uint32_t k = 0;
         for (int j = 0; j < t; j++)
             k += (len[j] == L);
-        const uint32_t code = first[L] + k;
-        dt->sorted[index[L] + k] = (uint8_t)t;
-        if (L <= kLutBits) {
-            const uint32_t lo = code << (kLutBits - L), hi = (code + 1) << (kLutBits - L);
-            for (uint32_t e = lo; e < hi && e < (1u << kLutBits); e++)
-                dt->lut[e] = (uint16_t)((L << 8) | t);
+        s_sorted[index[L] + k] = (uint8_t)t;
+    }
+    __syncthreads();
+    dt->sorted[t] = s_sorted[t];
+    // every table entry by itself: the shortest code that prefixes its index
+    for (uint32_t e = t; e < (1u << kLutBits); e += 256) {
+        uint16_t v = 0;
+        for (int b = 1; b <= kLutBits; b++) {
+            const uint32_t c = e >> (kLutBits - b);
+            if (blc[b] && c - first[b] < blc[b]) {
+                v = (uint16_t)((b << 8) | s_sorted[index[b] + (c - first[b])]);
+                break;
+            }
         }
+        dt->lut[e] = v;
     }
 }
 
@@ -756,7 +763,7 @@ void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s)
 // payload offset by look-back over the stored word counts, and each thread
 // decodes its chunk sequentially with the LDS lookup table.
 constexpr int kDecChunks = 256;
-constexpr int kWin = 32; // payload words per refill of a decoder's LDS window
+constexpr int kRing = 32; // payload words of a decoder lane's LDS ring (a power of two)
 
 __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, int njobs,
                                                 uint64_t total, Counters *cnt)
@@ -767,7 +774,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     __shared__ uint32_t s_id, s_maxlen;
     __shared__ uint64_t s_wsum[4];
     __shared__ uint64_t s_base;
-    __shared__ uint32_t s_win[kDecChunks * (kWin + 1)];
+    __shared__ uint32_t s_win[kDecChunks * (kRing + 1)];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (t == 0)
         s_id = atomicAdd(&cnt->dec_next, 1u);
@@ -817,7 +824,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     FieldState *st = J.st;
     const uint64_t start = s_base + before + incl - wc;
     const uint64_t pw = J.payload_words;
-    if (start + wc > pw) {
+    if (pw == 0 || start + wc > pw) {
         atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
         return;
     }
@@ -827,69 +834,128 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         reinterpret_cast<HIZ_GLOBAL const uint32_t *>(gmem(J.stream) + J.off_payload);
     HIZ_GLOBAL uint8_t *codes = gmem(J.codes);
     const uint64_t i0 = chunk << J.log2_chunk, i1 = min(i0 + J.chunk, J.N);
+    const uint32_t nsym = (uint32_t)(i1 - i0);
     const uint32_t maxlen = s_maxlen;
     const uint64_t wend = start + wc;
-    // payload words reach the decoder through a per-thread LDS window refilled
-    // with kWin independent loads at a time, so the sequential decode waits for
-    // memory once per window rather than once per word
-    uint32_t *mywin = s_win + t * (kWin + 1);
-    uint64_t wnext = start;
-    int wi = kWin;
+    // Payload words reach the decoder through a per-lane ring of kRing words in
+    // LDS. Symbols are decoded in blocks of 16, the same for every lane of the
+    // wave; at each block boundary the words prefetched during the previous
+    // block are committed to the ring and, if the ring has room, the next 16
+    // are requested. A block consumes at most 16 words (codewords are at most
+    // 32 bits), so the ring holding 16 words at a block's start is enough; a
+    // lane below that (codes far longer than usual) refills synchronously.
+    // Words past the chunk's end read as zero.
+    uint32_t *ring = s_win + t * (kRing + 1);
+    // payload word idx of this chunk, 0 past its end; the load itself is never
+    // skipped (its index is clamped inside the payload), so a run of them is
+    // issued back to back without a branch or a wait between them
+    const uint64_t wlast = wend > start ? wend - 1 : min(start, pw - 1);
+    auto raw = [&](uint64_t idx) -> uint32_t { return words[idx < wend ? idx : wlast]; };
+    auto word = [&](uint64_t idx) -> uint32_t { return idx < wend ? raw(idx) : 0u; };
+    uint64_t wfetch = start;
+    uint32_t rp = 0, wp = 0; // words read from / written to the ring so far
+    uint32_t pre[16];
+    uint64_t pre_base = 0; // payload index of pre[0]
+    bool pending = false;
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+        pre[j] = word(wfetch + j);
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+        ring[j] = pre[j];
+    wfetch += 16;
+    wp = 16;
     uint64_t buf = 0;
     int nb = 0;
     uint64_t used = 0;
-    uint32_t pack = 0, zeros = 0;
+    uint32_t zeros = 0;
     bool bad = false;
-    uint64_t i = i0;
-    for (; i < i1; i++) {
-        if (nb < 32) {
-            if (wi == kWin) {
-                uint32_t r[kWin];
+    // the next ring word waits in a register, so a refill of the bit buffer
+    // never waits for LDS; rp counts words taken out of the ring
+    uint32_t nextw = ring[0];
+    rp = 1;
+    const uint32_t nblk = (nsym + 15) >> 4;
+#pragma nounroll
+    for (uint32_t blk = 0; blk < nblk; blk++) {
+        // words requested a block ago enter the ring
+        if (pending) {
 #pragma unroll
-                for (int j = 0; j < kWin; j++)
-                    r[j] = wnext + j < wend ? words[wnext + j] : 0u;
-#pragma unroll
-                for (int j = 0; j < kWin; j++)
-                    mywin[j] = r[j];
-                wnext += kWin;
-                wi = 0;
-            }
-            const uint32_t wd = mywin[wi++];
-            buf |= (uint64_t)wd << (32 - nb);
-            nb += 32;
+            for (int j = 0; j < 16; j++)
+                ring[(wp + j) & (kRing - 1)] = pre_base + j < wend ? pre[j] : 0u;
+            wp += 16;
+            pending = false;
         }
-        const uint32_t e = lut[buf >> (64 - kLutBits)];
-        uint32_t L, sym;
-        if (e) {
-            L = e >> 8;
-            sym = e & 255u;
-        } else {
-            sym = 0;
-            for (L = kLutBits + 1; L <= maxlen; L++) {
-                const uint32_t c = (uint32_t)(buf >> (64 - L));
-                if (c - first[L] < count[L]) {
-                    sym = sorted[index[L] + (c - first[L])];
-                    break;
+        if (wp - rp < 16) {
+            // rare (codes far longer than usual): synchronous top-up
+            uint32_t r[16];
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                r[j] = word(wfetch + j);
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                ring[(wp + j) & (kRing - 1)] = r[j];
+            wfetch += 16;
+            wp += 16;
+        }
+        // request the next 16 words: decided per lane, but when any lane of
+        // the wave asks every lane loads (a uniform branch keeps the loads
+        // in flight until the next block commits them)
+        const bool want = wp - rp <= kRing - 16;
+        if (__any(want)) {
+            // raw words: the words past the chunk's end are zeroed when they
+            // are committed, so nothing here waits for the loads
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                pre[j] = raw(wfetch + j);
+            pre_base = wfetch;
+            if (want)
+                wfetch += 16;
+            pending = want;
+        }
+        uint32_t out[4] = {0u, 0u, 0u, 0u};
+        const uint32_t nk = min(16u, nsym - (blk << 4));
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (nb < 32) {
+                buf |= (uint64_t)nextw << (32 - nb);
+                nb += 32;
+                nextw = ring[rp & (kRing - 1)];
+                rp++;
+            }
+            const uint32_t e = lut[buf >> (64 - kLutBits)];
+            uint32_t L, sym;
+            if (e) {
+                L = e >> 8;
+                sym = e & 255u;
+            } else {
+                sym = 0;
+                for (L = kLutBits + 1; L <= maxlen; L++) {
+                    const uint32_t c = (uint32_t)(buf >> (64 - L));
+                    if (c - first[L] < count[L]) {
+                        sym = sorted[index[L] + (c - first[L])];
+                        break;
+                    }
+                }
+                if (L > maxlen) {
+                    bad = true;
+                    L = 1;
                 }
             }
-            if (L > maxlen) {
-                bad = true;
-                break;
+            if ((uint32_t)k < nk) {
+                buf <<= L;
+                nb -= (int)L;
+                used += L;
+                zeros += (sym == 0);
+                out[k >> 2] |= sym << (8 * (k & 3));
             }
         }
-        buf <<= L;
-        nb -= (int)L;
-        used += L;
-        zeros += (sym == 0);
-        pack |= sym << (8 * (i & 3));
-        if ((i & 3) == 3) {
-            *reinterpret_cast<HIZ_GLOBAL uint32_t *>(codes + i - 3) = pack;
-            pack = 0;
+        const uint64_t o = i0 + ((uint64_t)blk << 4);
+        if (nk == 16) {
+            gstore_u4(codes + o, make_uint4(out[0], out[1], out[2], out[3]));
+        } else {
+            for (uint32_t k = 0; k < nk; k++)
+                codes[o + k] = (uint8_t)(out[k >> 2] >> (8 * (k & 3)));
         }
-    }
-    if (!bad && (i1 & 3)) {
-        for (uint64_t k = i1 & ~uint64_t(3); k < i1; k++)
-            codes[k] = (uint8_t)(pack >> (8 * (k & 3)));
     }
     if (bad || (used + 31) / 32 != wc)
         atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
