@@ -91,6 +91,8 @@ struct Job {
     uint64_t *woff;      // encoder: payload word offset of each chunk
     uint64_t *zoff;      // encoder: first outlier slot of each chunk
     uint2 *mm_part;      // per-unit (min, max) key partials: minmax units (REL) or tiles (ABS)
+    float *crec;         // per full tile: values of its even-point grid after the coarse levels
+    uint8_t *ccode;      // per full tile: codes of its owned even points (compression)
     uint64_t dims[3];
     uint64_t N;
     uint32_t nb[3];      // blocks per axis = ceil(d / 16)
@@ -109,6 +111,9 @@ struct Job {
     uint64_t mm_begin, tune_begin, tile_begin, chunk_begin, group_begin, dblk_begin, out_begin;
     uint64_t n_mm, n_tune, n_tiles, n_groups, n_dblk;
     uint32_t n_full[3];  // full 17^3 blocks per axis (tuner sample)
+    uint32_t nf[3];      // full tiles per axis: coarse slot of tile (bx, by, bz0/TZ) is
+                         // (bx * nf[1] + by) * nf[2] + bz0/TZ
+    uint32_t pad3;
     uint32_t n_samples;  // tuner sample size
     // decompression: section layout and bound parsed from the header
     uint64_t off_oidx, off_oval, off_payload, n_out, payload_words;
@@ -158,6 +163,13 @@ void launch_decode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, 
 void launch_scatter(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s);
 void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
                         Counters *cnt, hipStream_t s);
+// Levels of stride 8, 4, 2 of every full tile on its grid of even points
+// (one wave per tile), ahead of k_predict / k_reconstruct.
+void launch_coarse(const Job *d_jobs, int njobs, uint64_t total, int tile_z, bool compress,
+                   hipStream_t s);
+// Values (4 bytes each) and codes of one tile's even-point grid.
+uint64_t coarse_values_per_tile(int tile_z);
+uint64_t coarse_codes_per_tile(int tile_z);
 int reconstruct_blocks_per_cu(int tile_z);
 
 // ---- device helpers shared by the kernels ----

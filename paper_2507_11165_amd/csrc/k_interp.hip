@@ -23,14 +23,19 @@ namespace hiz {
 __constant__ int8_t c_perm_i[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
                                       {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
-template <int TZ> struct TileShape {
-    static constexpr int EZ = 16 * TZ + 1;   // points along z incl. the far face
+// A tile of 1 x 1 x TZ blocks of edge BS (+1 shared face per axis) in LDS.
+// BS = 16 is the method's block; BS = 8 is the grid of its even points, on
+// which the levels of stride 8, 4, 2 are the same computation at half the
+// coordinates (strides 4, 2, 1).
+template <int TZ, int BS = 16> struct TileShape {
+    static constexpr int SIDE = BS + 1;      // points per block edge incl. the face
+    static constexpr int EZ = BS * TZ + 1;   // points along z incl. the far face
     static constexpr int PZ = EZ;            // LDS pitch of a z row (odd: spreads banks)
-    static constexpr int PX = kSide * PZ;    // LDS stride of x
-    static constexpr int NV = kSide * PX;    // values in the tile
-    static constexpr int OZ = 16 * TZ;       // owned points along z (full tile)
-    static constexpr int NC = 16 * 16 * OZ;  // owned codes
-    static constexpr int NROW = kSide * kSide;
+    static constexpr int PX = SIDE * PZ;     // LDS stride of x
+    static constexpr int NV = SIDE * PX;     // values in the tile
+    static constexpr int OZ = BS * TZ;       // owned points along z (full tile)
+    static constexpr int NC = BS * BS * OZ;  // owned codes
+    static constexpr int NROW = SIDE * SIDE;
 };
 
 struct Geo {
@@ -208,19 +213,19 @@ __device__ __forceinline__ float cross_eval(const CrossSamples &s, const CrossFl
 // x, y, z order is odd and used). nA: extent of the block along A (17 for
 // full blocks). The stride is a run-time value so that one compact code path
 // serves every level.
-template <int TZ, int A, int MB, int MC, bool CUB, bool COMP, bool FULL>
+template <int TZ, int A, int MB, int MC, bool CUB, bool COMP, bool FULL, int BS>
 __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restrict__ cb,
                                         const uint8_t *__restrict__ cl, const Geo &g, int x0,
                                         int y0, int z0, int nA, int S, const QParams &q)
 {
-    using TS = TileShape<TZ>;
+    using TS = TileShape<TZ, BS>;
     constexpr int B = (A == 0) ? 1 : 0;
     constexpr int C = (A == 2) ? 1 : 2;
     constexpr int stA = A == 0 ? TS::PX : (A == 1 ? TS::PZ : 1);
     constexpr int stB = B == 0 ? TS::PX : TS::PZ;
     constexpr int stC = C == 1 ? TS::PZ : 1;
     constexpr int M = (1 << A) | (MB << B) | (MC << C);
-    const int K = 8 >> __builtin_ctz(S);
+    const int K = (BS / 2) >> __builtin_ctz(S);
     const int last = nA - 1;
     const int li0 = x0 * TS::PX + y0 * TS::PZ + z0;
     // block bounds of the cross axes
@@ -229,8 +234,8 @@ __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restri
     const int hiB = (B == 0 ? g.ex : g.ey) - 1;
     int loC = 0, hiC;
     if constexpr (C == 2) {
-        loC = cC & ~15;
-        hiC = min(loC + 16, g.ez - 1);
+        loC = cC & ~(BS - 1);
+        hiC = min(loC + BS, g.ez - 1);
     } else {
         hiC = g.ey - 1;
     }
@@ -314,7 +319,7 @@ __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restri
             const uint8_t code = quantize(xv, p, q, xo);
             v[li] = xo;
             const bool own = x < g.ownx && y < g.owny && z < g.ownz;
-            cb[own ? (x * 16 + y) * TS::OZ + z : TS::NC] = code;
+            cb[own ? (x * BS + y) * TS::OZ + z : TS::NC] = code;
         } else {
             if (cc != 0)
                 v[li] = p + ((float)((int)cc - 128) * q.two_eb);
@@ -360,6 +365,7 @@ constexpr MagicTable make_magic_table()
 }
 __constant__ MagicTable c_magic = make_magic_table();
 __device__ __forceinline__ uint32_t qmagic(uint32_t d) { return c_magic.m[d]; }
+template <int V> constexpr int kLog2 = V <= 1 ? 0 : 1 + kLog2<V / 2>;
 
 // A group of lines of one kind: axis A plus which cross axes are odd and
 // interpolated (MD), with the coordinate modes of the two cross axes.
@@ -371,7 +377,7 @@ struct LineGroup {
 };
 
 __device__ __forceinline__ LineGroup make_group(int kind, int A, int modeB, int modeC, int S,
-                                                int ls, const Geo &g, int TZ)
+                                                int ls, const Geo &g, int TZ, int lbs)
 {
     LineGroup G;
     G.kind = kind;
@@ -383,7 +389,7 @@ __device__ __forceinline__ LineGroup make_group(int kind, int A, int modeB, int 
     G.cntB = mode_count(modeB, nB, ls);
     G.cntC = mode_count(modeC, nC, ls);
     if (A == 2)
-        G.ncell = g.ez - 1 >= S ? min(TZ, ((g.ez - 1 - S) >> 4) + 1) : 0;
+        G.ncell = g.ez - 1 >= S ? min(TZ, ((g.ez - 1 - S) >> lbs) + 1) : 0;
     else
         G.ncell = 1;
     if ((A == 0 && g.ex - 1 < S) || (A == 1 && g.ey - 1 < S))
@@ -397,7 +403,7 @@ __device__ __forceinline__ LineGroup make_group(int kind, int A, int modeB, int 
 // kinds: 0..2 plain lines along z, y, x; 3 along x with y odd (MD xy);
 // 4 along z with x odd (MD xz); 5 along z with y odd (MD yz); 6 along z with x
 // and y odd (MD xyz).
-template <int TZ, bool CUB, bool COMP, bool FULL>
+template <int TZ, bool CUB, bool COMP, bool FULL, int BS>
 __device__ __forceinline__ void run_line(const LineGroup &G, int l, int S, float *v, uint8_t *cb,
                                          const uint8_t *cl, const Geo &g, const QParams &q)
 {
@@ -409,20 +415,23 @@ __device__ __forceinline__ void run_line(const LineGroup &G, int l, int S, float
     const int cB = mode_coord(G.modeB, (int)iB, S);
     const int cC = mode_coord(G.modeC, (int)iC, S);
     if (G.A == 2) {
-        const int z0 = 16 * (int)cell;
-        const int nA = FULL ? 17 : min(17, g.ez - z0);
+        const int z0 = BS * (int)cell;
+        const int nA = FULL ? BS + 1 : min(BS + 1, g.ez - z0);
         switch (G.kind) {
-        case 0: do_line<TZ, 2, 0, 0, CUB, COMP, FULL>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
-        case 4: do_line<TZ, 2, 1, 0, CUB, COMP, FULL>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
-        case 5: do_line<TZ, 2, 0, 1, CUB, COMP, FULL>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
-        default: do_line<TZ, 2, 1, 1, CUB, COMP, FULL>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
+        case 0: do_line<TZ, 2, 0, 0, CUB, COMP, FULL, BS>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
+        case 4: do_line<TZ, 2, 1, 0, CUB, COMP, FULL, BS>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
+        case 5: do_line<TZ, 2, 0, 1, CUB, COMP, FULL, BS>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
+        default: do_line<TZ, 2, 1, 1, CUB, COMP, FULL, BS>(v, cb, cl, g, cB, cC, z0, nA, S, q); break;
         }
     } else if (G.A == 1) {
-        do_line<TZ, 1, 0, 0, CUB, COMP, FULL>(v, cb, cl, g, cB, 0, cC, FULL ? 17 : g.ey, S, q);
+        do_line<TZ, 1, 0, 0, CUB, COMP, FULL, BS>(v, cb, cl, g, cB, 0, cC, FULL ? BS + 1 : g.ey, S,
+                                                  q);
     } else if (G.kind == 3) {
-        do_line<TZ, 0, 1, 0, CUB, COMP, FULL>(v, cb, cl, g, 0, cB, cC, FULL ? 17 : g.ex, S, q);
+        do_line<TZ, 0, 1, 0, CUB, COMP, FULL, BS>(v, cb, cl, g, 0, cB, cC, FULL ? BS + 1 : g.ex, S,
+                                                  q);
     } else {
-        do_line<TZ, 0, 0, 0, CUB, COMP, FULL>(v, cb, cl, g, 0, cB, cC, FULL ? 17 : g.ex, S, q);
+        do_line<TZ, 0, 0, 0, CUB, COMP, FULL, BS>(v, cb, cl, g, 0, cB, cC, FULL ? BS + 1 : g.ex, S,
+                                                  q);
     }
 }
 
@@ -568,7 +577,7 @@ __device__ __forceinline__ void run_line_s1(const LineGroup &G, int l, float *v,
 // the j-th axis of the order every target whose last odd axis (in that order)
 // is that axis; axes earlier in the order take every multiple of S, later
 // ones even multiples only.
-template <int TZ, bool CUB, bool COMP, bool FULL>
+template <int TZ, bool CUB, bool COMP, bool FULL, int BS>
 __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g,
                                             int S, bool md, int perm, const QParams &q)
 {
@@ -578,17 +587,17 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
         int ng;
         if (md) {
             if (sub == 1) {
-                G0 = make_group(0, 2, M_EVEN, M_EVEN, S, ls, g, TZ);
-                G1 = make_group(1, 1, M_EVEN, M_EVEN, S, ls, g, TZ);
-                G2 = make_group(2, 0, M_EVEN, M_EVEN, S, ls, g, TZ);
+                G0 = make_group(0, 2, M_EVEN, M_EVEN, S, ls, g, TZ, kLog2<BS>);
+                G1 = make_group(1, 1, M_EVEN, M_EVEN, S, ls, g, TZ, kLog2<BS>);
+                G2 = make_group(2, 0, M_EVEN, M_EVEN, S, ls, g, TZ, kLog2<BS>);
                 ng = 3;
             } else if (sub == 2) {
-                G0 = make_group(3, 0, M_ODD, M_EVEN, S, ls, g, TZ);
-                G1 = make_group(4, 2, M_ODD, M_EVEN, S, ls, g, TZ);
-                G2 = make_group(5, 2, M_EVEN, M_ODD, S, ls, g, TZ);
+                G0 = make_group(3, 0, M_ODD, M_EVEN, S, ls, g, TZ, kLog2<BS>);
+                G1 = make_group(4, 2, M_ODD, M_EVEN, S, ls, g, TZ, kLog2<BS>);
+                G2 = make_group(5, 2, M_EVEN, M_ODD, S, ls, g, TZ, kLog2<BS>);
                 ng = 3;
             } else {
-                G0 = make_group(6, 2, M_ODD, M_ODD, S, ls, g, TZ);
+                G0 = make_group(6, 2, M_ODD, M_ODD, S, ls, g, TZ, kLog2<BS>);
                 G1 = G0;
                 G2 = G0;
                 ng = 1;
@@ -604,7 +613,7 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
             }
             const int modeB = earlyB ? M_ALL : M_EVEN;
             const int modeC = earlyC ? M_ALL : M_EVEN;
-            G0 = make_group(A == 2 ? 0 : (A == 1 ? 1 : 2), A, modeB, modeC, S, ls, g, TZ);
+            G0 = make_group(A == 2 ? 0 : (A == 1 ? 1 : 2), A, modeB, modeC, S, ls, g, TZ, kLog2<BS>);
             G1 = G0;
             G2 = G0;
             ng = 1;
@@ -612,8 +621,8 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
         const int n0 = G0.lines;
         const int n1 = n0 + (ng > 1 ? G1.lines : 0);
         const int n2 = n1 + (ng > 2 ? G2.lines : 0);
-        if (FULL && S == 1) {
-            if constexpr (FULL) {
+        if (FULL && BS == 16 && S == 1) {
+            if constexpr (FULL && BS == 16) {
                 for (int i = threadIdx.x; i < n2; i += blockDim.x) {
                     if (i < n0)
                         run_line_s1<TZ, CUB, COMP>(G0, i, v, cb, cl, g, q);
@@ -626,35 +635,35 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
         } else {
             for (int i = threadIdx.x; i < n2; i += blockDim.x) {
                 if (i < n0)
-                    run_line<TZ, CUB, COMP, FULL>(G0, i, S, v, cb, cl, g, q);
+                    run_line<TZ, CUB, COMP, FULL, BS>(G0, i, S, v, cb, cl, g, q);
                 else if (i < n1)
-                    run_line<TZ, CUB, COMP, FULL>(G1, i - n0, S, v, cb, cl, g, q);
+                    run_line<TZ, CUB, COMP, FULL, BS>(G1, i - n0, S, v, cb, cl, g, q);
                 else
-                    run_line<TZ, CUB, COMP, FULL>(G2, i - n1, S, v, cb, cl, g, q);
+                    run_line<TZ, CUB, COMP, FULL, BS>(G2, i - n1, S, v, cb, cl, g, q);
             }
         }
         __syncthreads();
     }
 }
 
-template <int TZ, bool COMP>
+template <int TZ, bool COMP, int BS = 16>
 __device__ __forceinline__ void level(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g, int S,
                                       const uint8_t *cfg, const QParams &q)
 {
     const bool cub = cfg[0] != 0;
     const bool md = cfg[1] == 0;
     const int perm = cfg[2];
-    const bool full = g.ex == kSide && g.ey == kSide && g.ez == 16 * TZ + 1;
+    const bool full = g.ex == BS + 1 && g.ey == BS + 1 && g.ez == BS * TZ + 1;
     if (cub) {
         if (full)
-            level_lines<TZ, true, COMP, true>(v, cb, cl, g, S, md, perm, q);
+            level_lines<TZ, true, COMP, true, BS>(v, cb, cl, g, S, md, perm, q);
         else
-            level_lines<TZ, true, COMP, false>(v, cb, cl, g, S, md, perm, q);
+            level_lines<TZ, true, COMP, false, BS>(v, cb, cl, g, S, md, perm, q);
     } else {
         if (full)
-            level_lines<TZ, false, COMP, true>(v, cb, cl, g, S, md, perm, q);
+            level_lines<TZ, false, COMP, true, BS>(v, cb, cl, g, S, md, perm, q);
         else
-            level_lines<TZ, false, COMP, false>(v, cb, cl, g, S, md, perm, q);
+            level_lines<TZ, false, COMP, false, BS>(v, cb, cl, g, S, md, perm, q);
     }
 }
 
@@ -695,33 +704,54 @@ __device__ __forceinline__ Geo tile_geometry(const Job &J, uint64_t lt, uint64_t
 // XCDs round-robin by blockIdx) owns a contiguous eighth of the tile list, so
 // tiles that share halo faces meet in the same L2, and its workgroups claim
 // tiles one at a time from a counter: a workgroup that meets slower tiles
-// (partial ones at the field's faces) simply takes fewer. The claimed index
-// goes through a two-slot LDS buffer so that a claim for the next tile never
-// overwrites the one some wave is still reading.
+// (partial ones at the field's faces) simply takes fewer. A workgroup whose
+// own eighth is exhausted goes on to the other XCDs' eighths, so an eighth
+// that holds more partial tiles does not hold up the launch. Thread 0 asks
+// for the next tile while the current one is processed; the index goes
+// through a two-slot LDS buffer so that it never overwrites the one some
+// wave is still reading.
 struct TileQueue {
-    uint64_t lo, hi;
-    uint32_t *ctr;
+    uint64_t total;
+    uint32_t *ctr; // eight counters, one per eighth
+    int home;      // this workgroup's XCD
+    int k;         // eighths tried so far (thread 0)
+    uint32_t ask;  // outstanding claim on eighth (home + k) & 7 (thread 0)
 };
+__device__ __forceinline__ uint64_t eighth_lo(uint64_t total, int x) { return total * x / 8; }
 __device__ __forceinline__ TileQueue tile_queue(uint64_t total, Counters *cnt)
 {
-    const uint32_t G = gridDim.x;
     TileQueue q;
-    if (G >= 8 && (G & 7) == 0) {
-        const uint32_t xcd = blockIdx.x & 7;
-        q.lo = total * xcd / 8;
-        q.hi = total * (xcd + 1) / 8;
-        q.ctr = &cnt->tile_next[xcd];
-    } else {
-        q.lo = 0;
-        q.hi = total;
-        q.ctr = &cnt->tile_next[0];
-    }
+    q.total = total;
+    q.ctr = cnt->tile_next;
+    q.home = (gridDim.x >= 8 && (gridDim.x & 7) == 0) ? (int)(blockIdx.x & 7) : 0;
+    q.k = 0;
+    q.ask = 0;
+    if (threadIdx.x == 0)
+        q.ask = atomicAdd(&q.ctr[q.home], 1u);
     return q;
 }
-__device__ __forceinline__ uint64_t claim_tile(const TileQueue &q, uint64_t *slot, int it)
+// Thread 0: resolve the outstanding claim into a tile index (total = none
+// left) and ask for the following one.
+__device__ __forceinline__ uint64_t next_tile(TileQueue &q)
+{
+    while (q.k < 8) {
+        const int x = (q.home + q.k) & 7;
+        const uint64_t lo = eighth_lo(q.total, x), hi = eighth_lo(q.total, x + 1);
+        if (lo + q.ask < hi) {
+            const uint64_t u = lo + q.ask;
+            q.ask = atomicAdd(&q.ctr[x], 1u);
+            return u;
+        }
+        q.k++;
+        if (q.k < 8)
+            q.ask = atomicAdd(&q.ctr[(q.home + q.k) & 7], 1u);
+    }
+    return q.total;
+}
+__device__ __forceinline__ uint64_t claim_tile(TileQueue &q, uint64_t *slot, int it)
 {
     if (threadIdx.x == 0)
-        slot[it & 1] = q.lo + atomicAdd(q.ctr, 1u);
+        slot[it & 1] = next_tile(q);
     __syncthreads();
     return slot[it & 1];
 }
@@ -757,7 +787,7 @@ __device__ __forceinline__ void load_tile_values(float *__restrict__ v,
         constexpr int PIECES = 4 * TZ + 1; // 4*TZ float4 pieces and the face element
         constexpr int ITEMS = TS::NROW * PIECES;
         // every piece of a thread in flight at once (one memory round trip)
-        constexpr int BATCH = (ITEMS + 255) / 256 < 12 ? (ITEMS + 255) / 256 : 12;
+        constexpr int BATCH = (ITEMS + 255) / 256 < 8 ? (ITEMS + 255) / 256 : 8;
 #pragma nounroll
         for (int i0 = 0; i0 < ITEMS; i0 += 256 * BATCH) {
             // pieces and face elements land in separate registers, so no
@@ -917,11 +947,69 @@ __device__ __forceinline__ void load_tile_codes(uint8_t *__restrict__ cl,
     }
 }
 
+// A full tile's even-point grid after the coarse levels (values, and for
+// compression the codes of its owned points) replaces the raw values in the
+// tile: its loads are issued ahead of the tile's own loads (coarse_fetch) and
+// written into LDS once the tile is there (coarse_place).
+template <int TZ, int NT> struct CoarseRegs {
+    using TC = TileShape<TZ, 8>;
+    static constexpr int IV = (TC::NV + NT - 1) / NT;
+    static constexpr int IC = (TC::NC + NT - 1) / NT;
+    float val[IV];
+    uint32_t code[IC];
+};
+template <int TZ, int NT>
+__device__ __forceinline__ void coarse_fetch(CoarseRegs<TZ, NT> &r, int tid,
+                                             HIZ_GLOBAL const float *__restrict__ crec,
+                                             HIZ_GLOBAL const uint8_t *__restrict__ ccode)
+{
+    using TC = TileShape<TZ, 8>;
+#pragma unroll
+    for (int k = 0; k < r.IV; k++) {
+        const int i = tid + NT * k;
+        r.val[k] = crec[i < TC::NV ? i : 0];
+    }
+    if (ccode) {
+#pragma unroll
+        for (int k = 0; k < r.IC; k++) {
+            const int i = tid + NT * k;
+            r.code[k] = ccode[i < TC::NC ? i : 0];
+        }
+    }
+}
+template <int TZ, int NT>
+__device__ __forceinline__ void coarse_place(const CoarseRegs<TZ, NT> &r, int tid,
+                                             float *__restrict__ v, uint8_t *__restrict__ cb)
+{
+    using TF = TileShape<TZ>;
+    using TC = TileShape<TZ, 8>;
+#pragma unroll
+    for (int k = 0; k < r.IV; k++) {
+        const int i = tid + NT * k;
+        if (i < TC::NV) {
+            const int zc = i % TC::PZ, q = i / TC::PZ;
+            const int yc = q % TC::SIDE, xc = q / TC::SIDE;
+            v[2 * xc * TF::PX + 2 * yc * TF::PZ + 2 * zc] = r.val[k];
+        }
+    }
+    if (cb) {
+#pragma unroll
+        for (int k = 0; k < r.IC; k++) {
+            const int i = tid + NT * k;
+            if (i < TC::NC) {
+                const int zc = i % TC::OZ, q = i / TC::OZ;
+                const int yc = q % 8, xc = q / 8;
+                cb[(2 * xc * 16 + 2 * yc) * TF::OZ + 2 * zc] = (uint8_t)r.code[k];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Compression: predict + quantize + histogram, persistent over tiles.
 // ---------------------------------------------------------------------------
 template <int TZ>
-__global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, int njobs,
+__global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs, int njobs,
                                                  uint64_t total, Counters *cnt)
 {
     using TS = TileShape<TZ>;
@@ -939,10 +1027,10 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
     const int t = threadIdx.x;
     hist[t] = 0;
     int cur = -1;
-    const TileQueue tq = tile_queue(total, cnt);
+    TileQueue tq = tile_queue(total, cnt);
     for (int it = 0;; it++) {
         const uint64_t u = claim_tile(tq, s_tile, it);
-        if (u >= tq.hi)
+        if (u >= total)
             break;
         const int ji = find_job<WK_TILE>(jobs, njobs, u);
         const Job &J = jobs[ji];
@@ -982,6 +1070,16 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
         uint32_t kmn = 0xffffffffu, kmx = 0u;
         bool bad = false;
         const bool vec = (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.field) & 15) == 0;
+        // a full tile's coarse levels ran ahead on its even-point grid
+        const bool coarse = J.crec && g.ex == kSide && g.ey == kSide && g.ez == TS::EZ;
+        CoarseRegs<TZ, 256> cr;
+        int ctid = t;
+        asm volatile("" : "+v"(ctid));
+        if (coarse) {
+            const uint64_t ci = ((uint64_t)bx * J.nf[1] + by) * J.nf[2] + bz0 / TZ;
+            coarse_fetch<TZ, 256>(cr, ctid, gmem(J.crec) + ci * TileShape<TZ, 8>::NV,
+                                  gmem(J.ccode) + ci * TileShape<TZ, 8>::NC);
+        }
         load_tile_values<TZ>(v, gmem(J.field), rowoff, g, vec, abs_mode, kmn, kmx, bad);
         if (abs_mode) {
             if (__any(bad) && (t & 63) == 0)
@@ -994,6 +1092,10 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
         // tile in LDS (the levels never write them)
         if (t < TZ && 16 * t < g.ownz)
             cb[t * 16] = 128;
+        if (coarse) {
+            __syncthreads();
+            coarse_place<TZ, 256>(cr, ctid, v, cb);
+        }
         __syncthreads();
         if (t < TZ && 16 * t < g.ownz) {
             const uint64_t ai = ((uint64_t)bx * J.nb[1] + by) * J.nb[2] + bz0 + t;
@@ -1001,7 +1103,10 @@ __global__ __launch_bounds__(256) void k_predict(const Job *__restrict__ jobs, i
             if (off + 4 <= J.cap)
                 *reinterpret_cast<HIZ_GLOBAL float *>(gmem(J.stream) + off) = v[16 * t];
         }
-        walk_levels<TZ, true>(v, cb, nullptr, g, cfg, qp);
+        if (coarse)
+            level<TZ, true>(v, cb, nullptr, g, 1, cfg[kLevels - 1], qp);
+        else
+            walk_levels<TZ, true>(v, cb, nullptr, g, cfg, qp);
         // codes of owned points -> global, histogram in LDS
         if (g.ownz == TS::OZ && (dz & 15) == 0) {
             for (int i = t; i < 16 * 16 * TZ; i += blockDim.x) {
@@ -1076,7 +1181,7 @@ int predict_blocks_per_cu(int tile_z)
 // Decompression: rebuild the tile from codes, anchors and outliers.
 // ---------------------------------------------------------------------------
 template <int TZ>
-__global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ jobs, int njobs,
+__global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ jobs, int njobs,
                                                      uint64_t total, Counters *cnt)
 {
     using TS = TileShape<TZ>;
@@ -1089,10 +1194,10 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
 
     const int t = threadIdx.x;
     int cur = -1;
-    const TileQueue tq = tile_queue(total, cnt);
+    TileQueue tq = tile_queue(total, cnt);
     for (int it = 0;; it++) {
         const uint64_t u = claim_tile(tq, s_tile, it);
-        if (u >= tq.hi)
+        if (u >= total)
             break;
         const int ji = find_job<WK_TILE>(jobs, njobs, u);
         const Job &J = jobs[ji];
@@ -1120,6 +1225,14 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
         HIZ_GLOBAL const float *anchors =
             reinterpret_cast<HIZ_GLOBAL const float *>(gmem(J.stream) + J.off_anchors);
         const bool vec = (dz & 15) == 0;
+        const bool coarse = J.crec && g.ex == kSide && g.ey == kSide && g.ez == TS::EZ;
+        CoarseRegs<TZ, 256> cr;
+        int ctid = t;
+        asm volatile("" : "+v"(ctid));
+        if (coarse) {
+            const uint64_t ci = ((uint64_t)bx * J.nf[1] + by) * J.nf[2] + bz0 / TZ;
+            coarse_fetch<TZ, 256>(cr, ctid, gmem(J.crec) + ci * TileShape<TZ, 8>::NV, nullptr);
+        }
         load_tile_codes<TZ>(cl, gmem(J.codes), rowoff, g, vec);
         // anchors of the tile region: every coordinate a multiple of 16
         if (t < 4 * (TZ + 1)) {
@@ -1162,7 +1275,13 @@ __global__ __launch_bounds__(256) void k_reconstruct(const Job *__restrict__ job
             }
         }
         __syncthreads();
-        walk_levels<TZ, false>(v, nullptr, cl, g, cfg, qp);
+        if (coarse) {
+            coarse_place<TZ, 256>(cr, ctid, v, nullptr);
+            __syncthreads();
+            level<TZ, false>(v, nullptr, cl, g, 1, cfg[kLevels - 1], qp);
+        } else {
+            walk_levels<TZ, false>(v, nullptr, cl, g, cfg, qp);
+        }
         if (g.ownz == TS::OZ && (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.out) & 15) == 0) {
             for (int i = t; i < 16 * 16 * 4 * TZ; i += blockDim.x) {
                 const int w = i % (4 * TZ), r = i / (4 * TZ);
@@ -1203,6 +1322,170 @@ void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t total, int tile_z
         launch_reconstruct_t<4>(d_jobs, njobs, total, grid, cnt, s);
     else
         launch_reconstruct_t<2>(d_jobs, njobs, total, grid, cnt, s);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse levels (strides 8, 4, 2) of every full tile, one wave per tile, on
+// the tile's grid of even points: 9 x 9 x (8 TZ + 1) values, the same
+// computation as in the full tile at half the coordinates (strides 4, 2, 1).
+// Many tiles per CU are in flight at once, so the serial chain of nine
+// sub-steps per tile overlaps across tiles instead of holding a full tile's
+// LDS. The results (values, and codes of the owned points for compression)
+// go to per-tile workspace slots for k_predict / k_reconstruct to overlay.
+// Partial tiles are left to the full kernels, which run all four levels.
+// ---------------------------------------------------------------------------
+template <int TZ, bool COMP>
+__global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int njobs,
+                                               uint64_t total)
+{
+    using TC = TileShape<TZ, 8>;
+    constexpr int IV = (TC::NV + 63) / 64;
+    __shared__ float v[TC::NV];
+    __shared__ __align__(16) uint8_t cb[TC::NC + 16];
+    __shared__ uint8_t cl[COMP ? 1 : TC::NV];
+    __shared__ uint8_t cfg[kLevels][3];
+    __shared__ QParams qp;
+    const int t = threadIdx.x;
+    for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
+        const Job &J = jobs[find_job<WK_TILE>(jobs, njobs, u)];
+        const FieldState *st = J.st;
+        if (COMP && (st->flags & (ST_CONST | ST_NONFINITE)))
+            continue;
+        uint64_t ox, oy, oz;
+        uint32_t bx, by, bz0;
+        const uint64_t lt = u - J.tile_begin;
+        const Geo gf = tile_geometry<TZ>(J, lt, ox, oy, oz, bx, by, bz0);
+        if (!(gf.ex == kSide && gf.ey == kSide && gf.ez == 16 * TZ + 1))
+            continue;
+        __syncthreads();
+        if (t == 0) {
+            qp.eps = st->eps;
+            qp.two_eb = st->two_eb;
+            qp.inv = COMP ? st->inv : 0.f;
+        }
+        if (t < kLevels * 3)
+            cfg[t / 3][t % 3] = st->cfg[t / 3][t % 3];
+        const uint64_t dy = J.dims[1], dz = J.dims[2];
+        auto gidx = [&](int i) -> uint64_t {
+            const int zc = i % TC::PZ, r = i / TC::PZ;
+            const int yc = r % TC::SIDE, xc = r / TC::SIDE;
+            return ((ox + 2 * xc) * dy + (oy + 2 * yc)) * dz + oz + 2 * zc;
+        };
+        // loads in batches of 8 per lane, each batch in flight at once; the
+        // lane index is opaque so its arithmetic is not kept across tiles
+        int tid = t;
+        asm volatile("" : "+v"(tid));
+        constexpr int B = 8;
+        if constexpr (COMP) {
+            HIZ_GLOBAL const float *field = gmem(J.field);
+#pragma nounroll
+            for (int i0 = 0; i0 < TC::NV; i0 += 64 * B) {
+                float val[B];
+#pragma unroll
+                for (int k = 0; k < B; k++) {
+                    const int i = i0 + tid + 64 * k;
+                    val[k] = field[gidx(i < TC::NV ? i : 0)];
+                }
+#pragma unroll
+                for (int k = 0; k < B; k++)
+                    if (i0 + tid + 64 * k < TC::NV)
+                        v[i0 + tid + 64 * k] = val[k];
+            }
+            if (t < TZ)
+                cb[8 * t] = 128; // anchors (0, 0, 8j)
+        } else {
+            // codes; anchors from the stream; outliers scattered into the output
+            HIZ_GLOBAL const uint8_t *codes = gmem(J.codes);
+            HIZ_GLOBAL const float *out = gmem(J.out);
+            HIZ_GLOBAL const float *anchors =
+                reinterpret_cast<HIZ_GLOBAL const float *>(gmem(J.stream) + J.off_anchors);
+#pragma nounroll
+            for (int i0 = 0; i0 < TC::NV; i0 += 64 * B) {
+                uint32_t c[B];
+#pragma unroll
+                for (int k = 0; k < B; k++) {
+                    const int i = i0 + tid + 64 * k;
+                    c[k] = codes[gidx(i < TC::NV ? i : 0)];
+                }
+                float ov[B];
+#pragma unroll
+                for (int k = 0; k < B; k++) {
+                    const int i = i0 + tid + 64 * k;
+                    const int zc = i % TC::PZ, r = i / TC::PZ;
+                    const int yc = r % TC::SIDE, xc = r / TC::SIDE;
+                    const bool anchor = (xc & 7) == 0 && (yc & 7) == 0 && (zc & 7) == 0;
+                    const uint64_t ai = ((uint64_t)(bx + (xc >> 3)) * J.nb[1] + (by + (yc >> 3))) *
+                                            J.nb[2] +
+                                        bz0 + (zc >> 3);
+                    ov[k] = 0.f;
+                    if (i < TC::NV && anchor)
+                        ov[k] = anchors[ai];
+                    else if (i < TC::NV && c[k] == 0)
+                        ov[k] = out[gidx(i)];
+                }
+#pragma unroll
+                for (int k = 0; k < B; k++) {
+                    const int i = i0 + tid + 64 * k;
+                    if (i < TC::NV) {
+                        cl[i] = (uint8_t)c[k];
+                        v[i] = ov[k];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const Geo gc = {TC::SIDE, TC::SIDE, TC::EZ, 8, 8, TC::OZ};
+#pragma unroll 1
+        for (int l = 0; l < kLevels - 1; l++) {
+            if constexpr (COMP)
+                level<TZ, true, 8>(v, cb, nullptr, gc, 4 >> l, cfg[l], qp);
+            else
+                level<TZ, false, 8>(v, nullptr, cl, gc, 4 >> l, cfg[l], qp);
+        }
+        const uint64_t ci = ((uint64_t)bx * J.nf[1] + by) * J.nf[2] + bz0 / TZ;
+        HIZ_GLOBAL float *crec = gmem(J.crec) + ci * TC::NV;
+        for (int i = t; i < TC::NV; i += 64)
+            crec[i] = v[i];
+        if constexpr (COMP) {
+            HIZ_GLOBAL uint8_t *cc = gmem(J.ccode) + ci * TC::NC;
+            for (int i = t; i < TC::NC / 16; i += 64)
+                gstore_u4(cc + 16 * i, *reinterpret_cast<const uint4 *>(&cb[16 * i]));
+        }
+    }
+}
+
+template <int TZ>
+static void launch_coarse_t(const Job *d_jobs, int njobs, uint64_t total, bool compress,
+                            hipStream_t s)
+{
+    const uint32_t g = (uint32_t)(total < (1u << 30) ? total : (1u << 30));
+    if (compress)
+        hipLaunchKernelGGL((k_coarse<TZ, true>), dim3(g), dim3(64), 0, s, d_jobs, njobs, total);
+    else
+        hipLaunchKernelGGL((k_coarse<TZ, false>), dim3(g), dim3(64), 0, s, d_jobs, njobs, total);
+}
+
+void launch_coarse(const Job *d_jobs, int njobs, uint64_t total, int tile_z, bool compress,
+                   hipStream_t s)
+{
+    if (total == 0)
+        return;
+    if (tile_z == 1)
+        launch_coarse_t<1>(d_jobs, njobs, total, compress, s);
+    else if (tile_z == 4)
+        launch_coarse_t<4>(d_jobs, njobs, total, compress, s);
+    else
+        launch_coarse_t<2>(d_jobs, njobs, total, compress, s);
+}
+
+uint64_t coarse_values_per_tile(int tile_z)
+{
+    return tile_z == 1 ? TileShape<1, 8>::NV : (tile_z == 4 ? TileShape<4, 8>::NV : TileShape<2, 8>::NV);
+}
+
+uint64_t coarse_codes_per_tile(int tile_z)
+{
+    return tile_z == 1 ? TileShape<1, 8>::NC : (tile_z == 4 ? TileShape<4, 8>::NC : TileShape<2, 8>::NC);
 }
 
 int reconstruct_blocks_per_cu(int tile_z)

@@ -460,6 +460,17 @@ hiz_status resolve_params(hiz_ctx *c, const hiz_params *params, hiz_params &p, i
     return HIZ_OK;
 }
 
+// Tiles whose blocks all have their +1 face inside the field, per axis: a
+// block starting at 16b is full when 16b + 16 < d.
+void set_full_tiles(Job &J, int tz)
+{
+    J.nf[0] = (uint32_t)((J.dims[0] - 1) / kAnchor);
+    J.nf[1] = (uint32_t)((J.dims[1] - 1) / kAnchor);
+    J.nf[2] = (uint32_t)((J.dims[2] - 1) / kAnchor / (uint64_t)tz);
+}
+
+uint64_t full_tiles(const Job &J) { return (uint64_t)J.nf[0] * J.nf[1] * J.nf[2]; }
+
 // Geometry and parameters of one field to compress; device pointers are
 // filled in by the caller once the workspace is laid out.
 hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode, double eb,
@@ -522,6 +533,7 @@ hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode,
     J.n_tune = (uint64_t)J.n_samples * 9;
     J.n_tiles = (uint64_t)J.nb[0] * J.nb[1] * J.ntz;
     J.n_groups = cdiv(J.n_chunks, kEncGroupChunks);
+    set_full_tiles(J, tz);
     return HIZ_OK;
 }
 
@@ -550,6 +562,7 @@ void plan_decompress(const Parsed &P, const void *d_in, uint64_t in_size, float 
     J.idx_bytes = (uint8_t)P.idx_bytes;
     J.n_tiles = (uint64_t)J.nb[0] * J.nb[1] * J.ntz;
     J.n_dblk = cdiv(J.n_chunks, 256);
+    set_full_tiles(J, tz);
     J.off_oidx = P.off_oidx;
     J.off_oval = P.off_oval;
     J.off_payload = P.off_payload;
@@ -574,7 +587,8 @@ struct Layout {
     uint8_t *h_res;
 };
 
-hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, Totals &T, Layout &L)
+hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, int tz, Totals &T,
+                  Layout &L)
 {
     const int nj = (int)jobs.size();
     Arena A;
@@ -582,12 +596,15 @@ hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, Totals &T
     const uint64_t o_cnt = A.take(sizeof(Counters));
     const uint64_t o_res = A.take((uint64_t)kResultBytes * nj);
     std::vector<uint64_t> o_st(nj), o_dt(nj), o_codes(nj), o_lba(nj), o_lbb(nj), o_woff(nj),
-        o_zoff(nj), o_mm(nj);
+        o_zoff(nj), o_mm(nj), o_crec(nj), o_ccode(nj);
+    const uint64_t cvals = coarse_values_per_tile(tz), ccodes = coarse_codes_per_tile(tz);
     T = Totals();
     for (int j = 0; j < nj; j++) {
         Job &J = jobs[j];
         o_st[j] = A.take(sizeof(FieldState));
         o_codes[j] = A.take(J.N);
+        o_crec[j] = A.take(4 * cvals * full_tiles(J));
+        o_ccode[j] = decompress ? 0 : A.take(ccodes * full_tiles(J));
         if (decompress) {
             o_dt[j] = A.take(sizeof(DecTables));
             o_lba[j] = A.take(8 * J.n_dblk);
@@ -631,6 +648,8 @@ hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, Totals &T
         Job &J = jobs[j];
         J.st = reinterpret_cast<FieldState *>(ws + o_st[j]);
         J.codes = ws + o_codes[j];
+        J.crec = reinterpret_cast<float *>(ws + o_crec[j]);
+        J.ccode = decompress ? nullptr : ws + o_ccode[j];
         J.lb_a = reinterpret_cast<uint64_t *>(ws + o_lba[j]);
         if (decompress) {
             J.dt = reinterpret_cast<DecTables *>(ws + o_dt[j]);
@@ -676,6 +695,10 @@ void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int 
         launch_tune_pick(L.d_jobs, nj, s);
     }
     {
+        Scope sc(c, s, "coarse", prof);
+        launch_coarse(L.d_jobs, nj, T.tiles, tz, true, s);
+    }
+    {
         Scope sc(c, s, "predict_quant", prof);
         launch_predict(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, false), L.d_cnt,
                        s);
@@ -712,6 +735,10 @@ void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, in
     if (T.out) {
         Scope sc(c, s, "scatter", prof);
         launch_scatter(L.d_jobs, nj, T.out, s);
+    }
+    {
+        Scope sc(c, s, "coarse_rec", prof);
+        launch_coarse(L.d_jobs, nj, T.tiles, tz, false, s);
     }
     {
         Scope sc(c, s, "reconstruct", prof);
@@ -868,7 +895,7 @@ hiz_status submit_compress(hiz_ctx *c, int n, const float *const *d_fields, cons
     if (B.njobs) {
         Totals T;
         Layout L;
-        rc = layout(c, jobs, false, T, L);
+        rc = layout(c, jobs, false, tz, T, L);
         if (rc)
             return abandon(c, s, rc);
         B.h_res = L.h_res;
@@ -967,7 +994,7 @@ hiz_status submit_decompress(hiz_ctx *c, int n, const void *const *d_ins,
     if (B.njobs) {
         Totals T;
         Layout L;
-        rc = layout(c, jobs, true, T, L);
+        rc = layout(c, jobs, true, tz, T, L);
         if (rc)
             return abandon(c, s, rc);
         B.h_res = L.h_res;
@@ -1132,9 +1159,16 @@ uint64_t hiz_workspace_bound(const uint64_t dims[3])
     const uint64_t groups = cdiv(chunks, kEncGroupChunks);
     const uint64_t tiles = cdiv(dims[0], kAnchor) * cdiv(dims[1], kAnchor) * cdiv(dims[2], kAnchor);
     const uint64_t mm = std::max<uint64_t>(cdiv(N, 16384), tiles);
-    const uint64_t per_job = sizeof(Job) + kResultBytes + sizeof(FieldState) + 10 * 256;
-    const uint64_t comp = per_job + N + 16 * groups + 16 * chunks + 8 * mm;
-    const uint64_t dec = per_job + sizeof(DecTables) + N + 8 * cdiv(chunks, 256);
+    const uint64_t per_job = sizeof(Job) + kResultBytes + sizeof(FieldState) + 12 * 256;
+    // per-tile coarse-level slots (values and codes of the even-point grid)
+    uint64_t coarse = 0;
+    for (int tz = 1; tz <= 4; tz *= 2) {
+        const uint64_t nt = ((dims[0] - 1) / kAnchor) * ((dims[1] - 1) / kAnchor) *
+                            ((dims[2] - 1) / kAnchor / tz);
+        coarse = std::max(coarse, nt * (4 * coarse_values_per_tile(tz) + coarse_codes_per_tile(tz)));
+    }
+    const uint64_t comp = per_job + N + 16 * groups + 16 * chunks + 8 * mm + coarse;
+    const uint64_t dec = per_job + sizeof(DecTables) + N + 8 * cdiv(chunks, 256) + coarse;
     return std::max(comp, dec);
 }
 
