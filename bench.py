@@ -49,21 +49,58 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(name, N, info, n_anchors):
+def algorithmic_bytes(name, N, info, n_anchors, shape, tile_z):
     """Bytes the method must move per launch of each kernel."""
     n_out = info["n_outliers"]
     pw = info["payload_words"]
     nch = info["n_chunks"]
     ib = 4 if N < 2 ** 32 else 8
+    # the coarse pre-pass: per full tile, the even-point grid's values read
+    # and written back, plus (compression) the owned even points' codes
+    nf = ((shape[0] - 1) // 16) * ((shape[1] - 1) // 16) * ((shape[2] - 1) // 16 // tile_z)
+    nv = 9 * 9 * (8 * tile_z + 1)
+    nc = 8 * 8 * 8 * tile_z
     table = {
         "minmax": 4 * N,
+        "coarse": nf * (8 * nv + nc),
         "predict_quant": 4 * N + N + 4 * n_anchors,
         "encode": N + 4 * pw + 4 * nch + (ib + 4) * n_out + 4 * n_out,
         "decode": 4 * pw + 4 * nch + N,
         "scatter": (ib + 4) * n_out + 4 * n_out,
+        "coarse_rec": nf * (nv + 8 * nv),
         "reconstruct": N + 4 * N + 4 * n_anchors + 4 * n_out,
     }
     return table.get(name)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "turb512_rel1e-3_hbm_traffic.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch (read + write) of a kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the summary is missing or the
+    kernel's sources changed since the counters were taken."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        f = line.split()
+        if len(f) < 6 or f[0] != "traffic" or f[1] != kernel:
+            continue
+        kv = dict(x.split("=", 1) for x in f[2:])
+        for ref in (kv["src"], kv["hdr"]):
+            fname, want = ref.split(":")
+            path = os.path.join(ROOT, "paper_2507_11165_amd", "csrc", fname)
+            try:
+                have = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+            except OSError:
+                return None
+            if have != want:
+                return None
+        return int(kv["read"]) + int(kv["write"])
+    return None
 
 
 def cpu_baseline(x, eb, planes):
@@ -198,12 +235,14 @@ def main():
             dom, dom_ms = name, ms
     launches, ms = prof[dom]
     mean_s = ms / launches / 1e3
-    algo = algorithmic_bytes(dom, N, info, n_anchors)
+    tz = args.tile_z or 2
+    algo = algorithmic_bytes(dom, N, info, n_anchors, shape, tz)
+    traffic = measured_traffic(dom) if tz == 2 and shape == (512, 512, 512) else None
     achieved = algo / mean_s / 1e9 if algo else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1) if achieved else None,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                "traffic": None, "algorithmic_bytes_per_launch": algo,
+                "traffic": traffic, "algorithmic_bytes_per_launch": algo,
                 "mean_launch_ms": round(mean_s * 1e3, 5)}
     value = 8.0 * N * args.steps / elapsed / 1e9
     res = {
