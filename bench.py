@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--cpu-planes", type=int, default=192)
+    ap.add_argument("--cpu-planes", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["turb512", "batch64", "serve"], default="turb512")
     ap.add_argument("--duration", type=float, default=5.0,
