@@ -914,20 +914,20 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         }
         uint32_t out[4] = {0u, 0u, 0u, 0u};
         const uint32_t nk = min(16u, nsym - (blk << 4));
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-            if (nb < 32) {
-                buf |= (uint64_t)nextw << (32 - nb);
-                nb += 32;
-                nextw = ring[rp & (kRing - 1)];
-                rp++;
-            }
+        // one symbol: refill the bit buffer without a branch (the ring word
+        // after nextw is read every time, used when a refill happens), look
+        // up the code, and consume it; only codes longer than the table
+        // branch off
+        auto step = [&](int k, bool active) {
+            const bool need = nb < 32;
+            const uint32_t nw = ring[rp & (kRing - 1)];
+            buf |= (uint64_t)(need ? nextw : 0u) << (need ? 32 - nb : 0);
+            nb += need ? 32 : 0;
+            nextw = need ? nw : nextw;
+            rp += need ? 1u : 0u;
             const uint32_t e = lut[buf >> (64 - kLutBits)];
-            uint32_t L, sym;
-            if (e) {
-                L = e >> 8;
-                sym = e & 255u;
-            } else {
+            uint32_t L = e >> 8, sym = e & 255u;
+            if (e == 0) {
                 sym = 0;
                 for (L = kLutBits + 1; L <= maxlen; L++) {
                     const uint32_t c = (uint32_t)(buf >> (64 - L));
@@ -941,13 +941,22 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
                     L = 1;
                 }
             }
-            if ((uint32_t)k < nk) {
+            if (active) {
                 buf <<= L;
                 nb -= (int)L;
                 used += L;
                 zeros += (sym == 0);
                 out[k >> 2] |= sym << (8 * (k & 3));
             }
+        };
+        if (nk == 16) {
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                step(k, true);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                step(k, (uint32_t)k < nk);
         }
         const uint64_t o = i0 + ((uint64_t)blk << 4);
         if (nk == 16) {
