@@ -188,6 +188,16 @@ template <class T> __device__ __forceinline__ HIZ_GLOBAL T *gmem(T *p)
 typedef float hiz_f4v __attribute__((ext_vector_type(4)));
 typedef uint32_t hiz_u4v __attribute__((ext_vector_type(4)));
 typedef uint32_t hiz_u2v __attribute__((ext_vector_type(2)));
+// Global memory straight into LDS, no registers in between: every lane of
+// the wave names its own 4-byte source, and the wave's 64 words land in order
+// at dst[0..63] (dst is the same for the whole wave). The loads count as
+// vector-memory loads: lds_fill_wait() retires them before a barrier makes
+// the words visible to the workgroup.
+__device__ __forceinline__ void lds_load_word(HIZ_GLOBAL const float *src, float *dst)
+{
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+}
+__device__ __forceinline__ void lds_fill_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ float4 gload_f4(HIZ_GLOBAL const float *p)
 {
     const hiz_f4v v = *(HIZ_GLOBAL const hiz_f4v *)p;

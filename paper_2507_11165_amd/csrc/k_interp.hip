@@ -753,116 +753,79 @@ __device__ __forceinline__ uint64_t claim_tile(TileQueue &q, uint64_t *slot, int
     if (threadIdx.x == 0)
         slot[it & 1] = next_tile(q);
     __syncthreads();
-    return slot[it & 1];
+    // the same for every lane: job lookups and job fields go to scalar loads
+    const uint64_t u = slot[it & 1];
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32)) << 32) |
+           __builtin_amdgcn_readfirstlane((uint32_t)u);
 }
 
 // ---------------------------------------------------------------------------
-// Tile I/O. Each thread issues all of its global loads before it writes any
-// of them to LDS, so a tile costs one memory round trip rather than one per
-// element. Rows are read as 16-byte pieces where the field's rows are
-// 16-byte aligned (dz a multiple of 4 for floats, of 16 for codes).
+// Tile I/O. Values go from global memory straight into LDS, every load of
+// the tile in flight at once. For codes each thread issues all of its global
+// loads before it writes any of them to LDS, so a tile costs one memory round
+// trip rather than one per element; rows are read as 16-byte pieces where
+// the field's rows are 16-byte aligned (dz a multiple of 16).
 // ---------------------------------------------------------------------------
+// LDS words dst[(x * SIDE + y) * PZ + z], e < N, from global offsets
+// base + x * sx + y * sy + z * sz. Wave w of NW issues loads w, w + NW, ...
+// (64 words each); a lane's coordinates and offset advance incrementally. In
+// a partial tile (full false) words outside the extents ex, ey, ez take the
+// value at base and are never read.
+template <int N, int PZ, int SIDE, int NW>
+__device__ __forceinline__ void lds_fill_tile(float *__restrict__ dst,
+                                              HIZ_GLOBAL const float *__restrict__ src,
+                                              uint64_t base, uint64_t sx, uint64_t sy, uint64_t sz,
+                                              bool full, int ex, int ey, int ez)
+{
+    constexpr int NJ = (N + 63) / 64;
+    constexpr int STEP = 64 * NW, DR = STEP / PZ, DZ = STEP % PZ;
+    static_assert(DR < SIDE, "one step crosses at most one row of rows");
+    const int wave = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int e0 = 64 * wave + lane;
+    int z = e0 % PZ, r = e0 / PZ;
+    int y = r % SIDE, x = r / SIDE;
+    uint64_t off = base + (uint64_t)x * sx + (uint64_t)y * sy + (uint64_t)z * sz;
+    // offset steps (unsigned wrap-around where a step goes backwards)
+    const uint64_t d0 = (uint64_t)DR * sy + (uint64_t)DZ * sz;
+    const uint64_t dzw = sy - (uint64_t)PZ * sz;
+    const uint64_t dyw = sx - (uint64_t)SIDE * sy;
+#pragma unroll 2
+    for (int j = wave; j < NJ; j += NW) {
+        const bool in = full || (x < ex && y < ey && z < ez);
+        if (N % 64 == 0 || j < NJ - 1 || 64 * j + lane < N)
+            lds_load_word(src + (in ? off : base), dst + 64 * j);
+        z += DZ;
+        y += DR;
+        off += d0;
+        if (z >= PZ) {
+            z -= PZ;
+            y += 1;
+            off += dzw;
+        }
+        if (y >= SIDE) {
+            y -= SIDE;
+            x += 1;
+            off += dyw;
+        }
+    }
+}
+
+// Extremes (as order keys) and finiteness of the tile's values in LDS.
 template <int TZ>
-__device__ __forceinline__ void load_tile_values(float *__restrict__ v,
-                                                 HIZ_GLOBAL const float *__restrict__ field,
-                                                 const uint64_t *rowoff, const Geo &g, bool vec,
-                                                 bool track, uint32_t &kmn, uint32_t &kmx,
-                                                 bool &bad)
+__device__ __forceinline__ void scan_tile_values(const float *__restrict__ v, const Geo &g,
+                                                 uint32_t &kmn, uint32_t &kmx, bool &bad)
 {
     using TS = TileShape<TZ>;
-    auto note = [&](float val) {
-        if (track) {
+    for (int e = threadIdx.x; e < TS::NV; e += blockDim.x) {
+        const int r = e / TS::PZ, z = e - r * TS::PZ;
+        const int x = r / kSide, y = r - x * kSide;
+        if (x < g.ex && y < g.ey && z < g.ez) {
+            const float val = v[e];
             bad |= !isfinite(val);
             const uint32_t k = fkey(val);
             kmn = min(kmn, k);
             kmx = max(kmx, k);
-        }
-    };
-    // the thread index passes through an empty asm so that the per-piece
-    // index arithmetic is redone per tile instead of being hoisted out of the
-    // persistent tile loop into dozens of long-lived registers
-    int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    if (vec) {
-        constexpr int PIECES = 4 * TZ + 1; // 4*TZ float4 pieces and the face element
-        constexpr int ITEMS = TS::NROW * PIECES;
-        // every piece of a thread in flight at once (one memory round trip)
-        constexpr int BATCH = (ITEMS + 255) / 256 < 8 ? (ITEMS + 255) / 256 : 8;
-#pragma nounroll
-        for (int i0 = 0; i0 < ITEMS; i0 += 256 * BATCH) {
-            // pieces and face elements land in separate registers, so no
-            // load has to complete before another branch writes its target
-            float4 buf[BATCH];
-            float face[BATCH];
-#pragma unroll
-            for (int k = 0; k < BATCH; k++) {
-                const int i = i0 + tid + 256 * k;
-                const int r = i / PIECES, pc = i - r * PIECES;
-                const int y = r % kSide, x = r / kSide;
-                buf[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-                face[k] = 0.f;
-                const bool row = i < ITEMS && x < g.ex && y < g.ey;
-                HIZ_GLOBAL const float *rp = field + rowoff[row ? r : 0];
-                if (row && pc < 4 * TZ && 4 * pc + 4 <= g.ez)
-                    buf[k] = gload_f4(rp + 4 * pc);
-                if (row && pc == 4 * TZ && 16 * TZ < g.ez)
-                    face[k] = rp[16 * TZ];
-            }
-#pragma unroll
-            for (int k = 0; k < BATCH; k++) {
-                const int i = i0 + tid + 256 * k;
-                const int r = i / PIECES, pc = i - r * PIECES;
-                const int y = r % kSide, x = r / kSide;
-                if (i < ITEMS && x < g.ex && y < g.ey) {
-                    float *vp = v + x * TS::PX + y * TS::PZ;
-                    if (pc < 4 * TZ) {
-                        const int z0 = 4 * pc;
-                        if (z0 + 4 <= g.ez) {
-                            const float e[4] = {buf[k].x, buf[k].y, buf[k].z, buf[k].w};
-#pragma unroll
-                            for (int j = 0; j < 4; j++) {
-                                vp[z0 + j] = e[j];
-                                note(e[j]);
-                            }
-                        } else {
-                            // a row cut short by the field boundary (rare)
-                            for (int z = z0; z < g.ez; z++) {
-                                const float e = field[rowoff[r] + z];
-                                vp[z] = e;
-                                note(e);
-                            }
-                        }
-                    } else if (16 * TZ < g.ez) {
-                        vp[16 * TZ] = face[k];
-                        note(face[k]);
-                    }
-                }
-            }
-        }
-    } else {
-        constexpr int NE = TS::NROW * TS::EZ;
-#pragma nounroll
-        for (int i0 = 0; i0 < NE; i0 += 256 * 8) {
-            float b[8];
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const int i = i0 + tid + 256 * k;
-                const int z = i % TS::EZ, r = i / TS::EZ;
-                const int y = r % kSide, x = r / kSide;
-                b[k] = 0.f;
-                if (i < NE && x < g.ex && y < g.ey && z < g.ez)
-                    b[k] = field[rowoff[r] + z];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const int i = i0 + tid + 256 * k;
-                const int z = i % TS::EZ, r = i / TS::EZ;
-                const int y = r % kSide, x = r / kSide;
-                if (i < NE && x < g.ex && y < g.ey && z < g.ez) {
-                    v[x * TS::PX + y * TS::PZ + z] = b[k];
-                    note(b[k]);
-                }
-            }
         }
     }
 }
@@ -954,7 +917,7 @@ __device__ __forceinline__ void load_tile_codes(uint8_t *__restrict__ cl,
 template <int TZ, int NT> struct CoarseRegs {
     using TC = TileShape<TZ, 8>;
     static constexpr int IV = (TC::NV + NT - 1) / NT;
-    static constexpr int IC = (TC::NC + NT - 1) / NT;
+    static constexpr int IC = (TC::NC / 4 + NT - 1) / NT; // 4-byte words
     float val[IV];
     uint32_t code[IC];
 };
@@ -964,16 +927,18 @@ __device__ __forceinline__ void coarse_fetch(CoarseRegs<TZ, NT> &r, int tid,
                                              HIZ_GLOBAL const uint8_t *__restrict__ ccode)
 {
     using TC = TileShape<TZ, 8>;
+    static_assert(TC::NC % 4 == 0 && TC::OZ % 4 == 0, "code words hold 4 points of a row");
 #pragma unroll
     for (int k = 0; k < r.IV; k++) {
         const int i = tid + NT * k;
         r.val[k] = crec[i < TC::NV ? i : 0];
     }
     if (ccode) {
+        HIZ_GLOBAL const uint32_t *cw = reinterpret_cast<HIZ_GLOBAL const uint32_t *>(ccode);
 #pragma unroll
         for (int k = 0; k < r.IC; k++) {
             const int i = tid + NT * k;
-            r.code[k] = ccode[i < TC::NC ? i : 0];
+            r.code[k] = cw[i < TC::NC / 4 ? i : 0];
         }
     }
 }
@@ -995,11 +960,14 @@ __device__ __forceinline__ void coarse_place(const CoarseRegs<TZ, NT> &r, int ti
     if (cb) {
 #pragma unroll
         for (int k = 0; k < r.IC; k++) {
-            const int i = tid + NT * k;
+            const int i = 4 * (tid + NT * k);
             if (i < TC::NC) {
                 const int zc = i % TC::OZ, q = i / TC::OZ;
                 const int yc = q % 8, xc = q / 8;
-                cb[(2 * xc * 16 + 2 * yc) * TF::OZ + 2 * zc] = (uint8_t)r.code[k];
+                uint8_t *c = cb + (2 * xc * 16 + 2 * yc) * TF::OZ + 2 * zc;
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+                    c[2 * b] = (uint8_t)(r.code[k] >> (8 * b));
             }
         }
     }
@@ -1015,7 +983,6 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
     using TS = TileShape<TZ>;
     __shared__ float v[TS::NV];
     __shared__ __align__(16) uint8_t cb[TS::NC + 16]; // + a dummy slot for faces
-    __shared__ uint64_t rowoff[TS::NROW];
     __shared__ uint32_t hist[256];
     __shared__ uint8_t cfg[kLevels][3];
     __shared__ QParams qp;
@@ -1060,16 +1027,8 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
         uint32_t bx, by, bz0;
         const Geo g = tile_geometry<TZ>(J, u - J.tile_begin, ox, oy, oz, bx, by, bz0);
         const uint64_t dy = J.dims[1], dz = J.dims[2];
-        for (int r = t; r < TS::NROW; r += blockDim.x) {
-            const int x = r / kSide, y = r % kSide;
-            rowoff[r] = ((ox + x) * dy + (oy + y)) * dz + oz;
-        }
-        __syncthreads();
-        // load the tile (with its +1 faces) into LDS
+        const uint64_t sx = dy * dz, base = (ox * dy + oy) * dz + oz;
         const bool abs_mode = J.mode == 0;
-        uint32_t kmn = 0xffffffffu, kmx = 0u;
-        bool bad = false;
-        const bool vec = (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.field) & 15) == 0;
         // a full tile's coarse levels ran ahead on its even-point grid
         const bool coarse = J.crec && g.ex == kSide && g.ey == kSide && g.ez == TS::EZ;
         CoarseRegs<TZ, 256> cr;
@@ -1080,23 +1039,30 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
             coarse_fetch<TZ, 256>(cr, ctid, gmem(J.crec) + ci * TileShape<TZ, 8>::NV,
                                   gmem(J.ccode) + ci * TileShape<TZ, 8>::NC);
         }
-        load_tile_values<TZ>(v, gmem(J.field), rowoff, g, vec, abs_mode, kmn, kmx, bad);
+        // the tile (with its +1 faces) into LDS
+        lds_fill_tile<TS::NV, TS::PZ, kSide, 4>(v, gmem(J.field), base, sx, dz, 1,
+                                                g.ex == kSide && g.ey == kSide && g.ez == TS::EZ,
+                                                g.ex, g.ey, g.ez);
+        // anchors owned by this tile: local (0, 0, 16j), stored raw from the
+        // tile in LDS (the levels never write them)
+        if (t < TZ && 16 * t < g.ownz)
+            cb[t * 16] = 128;
+        lds_fill_wait();
+        __syncthreads();
         if (abs_mode) {
+            uint32_t kmn = 0xffffffffu, kmx = 0u;
+            bool bad = false;
+            scan_tile_values<TZ>(v, g, kmn, kmx, bad);
             if (__any(bad) && (t & 63) == 0)
                 atomicOr(&J.st->flags, (uint32_t)ST_NONFINITE);
             block_minmax(kmn, kmx, red);
             if (t == 0)
                 gstore_u2(gmem(J.mm_part) + (u - J.tile_begin), make_uint2(kmn, kmx));
         }
-        // anchors owned by this tile: local (0, 0, 16j), stored raw from the
-        // tile in LDS (the levels never write them)
-        if (t < TZ && 16 * t < g.ownz)
-            cb[t * 16] = 128;
         if (coarse) {
-            __syncthreads();
             coarse_place<TZ, 256>(cr, ctid, v, cb);
+            __syncthreads();
         }
-        __syncthreads();
         if (t < TZ && 16 * t < g.ownz) {
             const uint64_t ai = ((uint64_t)bx * J.nb[1] + by) * J.nb[2] + bz0 + t;
             const uint64_t off = J.off_anchors + 4 * ai;
@@ -1114,7 +1080,7 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
                     const uint4 c16 = *reinterpret_cast<const uint4 *>(&cb[r * TS::OZ + 16 * w]);
-                    gstore_u4(gmem(J.codes) + rowoff[x * kSide + y] + 16 * w, c16);
+                    gstore_u4(gmem(J.codes) + base + x * sx + y * dz + 16 * w, c16);
                     const uint32_t cw[4] = {c16.x, c16.y, c16.z, c16.w};
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
@@ -1131,7 +1097,7 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny && z < g.ownz) {
                     const uint8_t c = cb[r * TS::OZ + z];
-                    gmem(J.codes)[rowoff[x * kSide + y] + z] = c;
+                    gmem(J.codes)[base + x * sx + y * dz + z] = c;
                     atomicAdd(&hist[c], 1u);
                 }
             }
@@ -1371,26 +1337,14 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
             const int yc = r % TC::SIDE, xc = r / TC::SIDE;
             return ((ox + 2 * xc) * dy + (oy + 2 * yc)) * dz + oz + 2 * zc;
         };
-        // loads in batches of 8 per lane, each batch in flight at once; the
-        // lane index is opaque so its arithmetic is not kept across tiles
+        // the lane index is opaque so its arithmetic is not kept across tiles
         int tid = t;
         asm volatile("" : "+v"(tid));
         constexpr int B = 8;
         if constexpr (COMP) {
-            HIZ_GLOBAL const float *field = gmem(J.field);
-#pragma nounroll
-            for (int i0 = 0; i0 < TC::NV; i0 += 64 * B) {
-                float val[B];
-#pragma unroll
-                for (int k = 0; k < B; k++) {
-                    const int i = i0 + tid + 64 * k;
-                    val[k] = field[gidx(i < TC::NV ? i : 0)];
-                }
-#pragma unroll
-                for (int k = 0; k < B; k++)
-                    if (i0 + tid + 64 * k < TC::NV)
-                        v[i0 + tid + 64 * k] = val[k];
-            }
+            // the even points straight into LDS, all in flight at once
+            lds_fill_tile<TC::NV, TC::PZ, TC::SIDE, 1>(v, gmem(J.field), (ox * dy + oy) * dz + oz,
+                                                       2 * dy * dz, 2 * dz, 2, true, 0, 0, 0);
             if (t < TZ)
                 cb[8 * t] = 128; // anchors (0, 0, 8j)
         } else {
@@ -1433,6 +1387,7 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
                 }
             }
         }
+        lds_fill_wait();
         __syncthreads();
         const Geo gc = {TC::SIDE, TC::SIDE, TC::EZ, 8, 8, TC::OZ};
 #pragma unroll 1
