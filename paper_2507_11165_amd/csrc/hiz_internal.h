@@ -197,6 +197,14 @@ __device__ __forceinline__ void lds_load_word(HIZ_GLOBAL const float *src, float
 {
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
 }
+// Workgroup barrier for data exchanged through LDS only: LDS operations
+// retire first, global loads and stores stay in flight across it (a
+// __syncthreads() would also wait for every outstanding global access, such
+// as the next tile's loads issued ahead of time).
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 __device__ __forceinline__ void lds_fill_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ float4 gload_f4(HIZ_GLOBAL const float *p)
 {

@@ -20,8 +20,10 @@
 
 namespace hiz {
 
-__constant__ int8_t c_perm_i[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
-                                      {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+// axis orders of the sequential scheme (32-bit entries: read with scalar
+// loads, which do not wait for vector-memory loads in flight)
+__constant__ int32_t c_perm_i[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
+                                       {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
 // A tile of 1 x 1 x TZ blocks of edge BS (+1 shared face per axis) in LDS.
 // BS = 16 is the method's block; BS = 8 is the grid of its even points, on
@@ -364,7 +366,12 @@ constexpr MagicTable make_magic_table()
     return t;
 }
 __constant__ MagicTable c_magic = make_magic_table();
-__device__ __forceinline__ uint32_t qmagic(uint32_t d) { return c_magic.m[d]; }
+// d is the same for the whole workgroup: the lookup is a scalar load, which
+// does not wait for the vector-memory loads in flight
+__device__ __forceinline__ uint32_t qmagic(uint32_t d)
+{
+    return c_magic.m[__builtin_amdgcn_readfirstlane(d)];
+}
 template <int V> constexpr int kLog2 = V <= 1 ? 0 : 1 + kLog2<V / 2>;
 
 // A group of lines of one kind: axis A plus which cross axes are odd and
@@ -581,6 +588,10 @@ template <int TZ, bool CUB, bool COMP, bool FULL, int BS>
 __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g,
                                             int S, bool md, int perm, const QParams &q)
 {
+    // workgroup size: 256 threads for blocks of 16, one wave for the
+    // even-point grid (a constant, so no load of the launch size waits on
+    // the vector-memory loads in flight)
+    constexpr int NT = BS == 16 ? 256 : 64;
     const int ls = __builtin_ctz(S);
     for (int sub = 1; sub <= 3; sub++) {
         LineGroup G0, G1, G2;
@@ -603,6 +614,8 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
                 ng = 1;
             }
         } else {
+            // uniform index: scalar loads of the table
+            perm = __builtin_amdgcn_readfirstlane(perm);
             const int A = c_perm_i[perm][sub - 1];
             const int B = A == 0 ? 1 : 0, C = A == 2 ? 1 : 2;
             // an axis placed before A in the order may be odd or even
@@ -623,7 +636,7 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
         const int n2 = n1 + (ng > 2 ? G2.lines : 0);
         if (FULL && BS == 16 && S == 1) {
             if constexpr (FULL && BS == 16) {
-                for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+                for (int i = threadIdx.x; i < n2; i += NT) {
                     if (i < n0)
                         run_line_s1<TZ, CUB, COMP>(G0, i, v, cb, cl, g, q);
                     else if (i < n1)
@@ -633,7 +646,7 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
                 }
             }
         } else {
-            for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+            for (int i = threadIdx.x; i < n2; i += NT) {
                 if (i < n0)
                     run_line<TZ, CUB, COMP, FULL, BS>(G0, i, S, v, cb, cl, g, q);
                 else if (i < n1)
@@ -642,7 +655,7 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
                     run_line<TZ, CUB, COMP, FULL, BS>(G2, i - n1, S, v, cb, cl, g, q);
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -752,7 +765,7 @@ __device__ __forceinline__ uint64_t claim_tile(TileQueue &q, uint64_t *slot, int
 {
     if (threadIdx.x == 0)
         slot[it & 1] = next_tile(q);
-    __syncthreads();
+    lds_barrier();
     // the same for every lane: job lookups and job fields go to scalar loads
     const uint64_t u = slot[it & 1];
     return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32)) << 32) |
@@ -817,7 +830,7 @@ __device__ __forceinline__ void scan_tile_values(const float *__restrict__ v, co
                                                  uint32_t &kmn, uint32_t &kmx, bool &bad)
 {
     using TS = TileShape<TZ>;
-    for (int e = threadIdx.x; e < TS::NV; e += blockDim.x) {
+    for (int e = threadIdx.x; e < TS::NV; e += 256) {
         const int r = e / TS::PZ, z = e - r * TS::PZ;
         const int x = r / kSide, y = r - x * kSide;
         if (x < g.ex && y < g.ey && z < g.ez) {
@@ -973,14 +986,128 @@ __device__ __forceinline__ void coarse_place(const CoarseRegs<TZ, NT> &r, int ti
     }
 }
 
+// A tile's values (and, for a full tile, its coarse-grid results) fetched
+// into registers while the previous tile is computed. Rows of the tile are
+// read as 16-byte pieces (thread t holds pieces t + 256 k, a piece being four
+// consecutive z of one (x, y) row) plus the far z face one point per row;
+// this needs rows that start 16-byte aligned and tiles that hold every piece
+// (the tile's z extent at least 16 * TZ). Other tiles are loaded straight
+// into LDS when they are placed. Used where the registers fit next to the
+// levels' (tiles of one or two blocks).
+template <int TZ> struct TileRegs {
+    static constexpr int NP = kSide * kSide * 4 * TZ; // pieces
+    static constexpr int IP = (NP + 255) / 256;
+    static constexpr int NF = kSide * kSide; // far-face points
+    static constexpr int IF = (NF + 255) / 256;
+    float4 piece[IP];
+    float face[IF];
+    CoarseRegs<TZ, 256> cr;
+    bool vec; // pieces fetched (else the tile is loaded when placed)
+};
+template <int TZ> constexpr bool kPrefetchTiles = TZ <= 2;
+
+template <int TZ>
+__device__ __forceinline__ void tile_fetch(TileRegs<TZ> &f, const Job &J, uint64_t u, int tid)
+{
+    using TS = TileShape<TZ>;
+    using TR = TileRegs<TZ>;
+    // the lane's coordinate sequence depends on the thread index alone: made
+    // opaque here so that it is recomputed per tile rather than hoisted out
+    // of the tile loop into dozens of long-lived registers
+    asm volatile("" : "+v"(tid));
+    uint64_t ox, oy, oz;
+    uint32_t bx, by, bz0;
+    const Geo g = tile_geometry<TZ>(J, u - J.tile_begin, ox, oy, oz, bx, by, bz0);
+    const uint64_t dy = J.dims[1], dz = J.dims[2];
+    const uint64_t sx = dy * dz, base = (ox * dy + oy) * dz + oz;
+    const bool full = g.ex == kSide && g.ey == kSide && g.ez == TS::EZ;
+    f.vec = (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.field) & 15) == 0 &&
+            g.ez >= 16 * TZ;
+    if (J.crec && full) {
+        const uint64_t ci = ((uint64_t)bx * J.nf[1] + by) * J.nf[2] + bz0 / TZ;
+        coarse_fetch<TZ, 256>(f.cr, tid, gmem(J.crec) + ci * TileShape<TZ, 8>::NV,
+                              gmem(J.ccode) + ci * TileShape<TZ, 8>::NC);
+    }
+    if (!f.vec)
+        return;
+    HIZ_GLOBAL const float *field = gmem(J.field);
+    // piece t + 256 k: row r = t / (4 TZ) + k * 64 / TZ, z = 4 * (t % (4 TZ))
+    constexpr int RS = 64 / TZ, DX = RS / kSide, DY = RS % kSide;
+    int r = tid / (4 * TZ);
+    int y = r % kSide, x = r / kSide;
+    uint64_t off = base + (uint64_t)x * sx + (uint64_t)y * dz + 4 * (tid % (4 * TZ));
+    const uint64_t d0 = DX * sx + DY * dz, dyw = sx - kSide * dz;
+#pragma unroll
+    for (int k = 0; k < TR::IP; k++) {
+        const bool in = (k < TR::IP - 1 || tid + 256 * k < TR::NP) &&
+                        (full || (x < g.ex && y < g.ey));
+        f.piece[k] = gload_f4(field + (in ? off : base));
+        x += DX;
+        y += DY;
+        off += d0;
+        if (y >= kSide) {
+            y -= kSide;
+            x += 1;
+            off += dyw;
+        }
+    }
+    // far face: row t + 256 k, z = 16 TZ
+#pragma unroll
+    for (int k = 0; k < TR::IF; k++) {
+        const int rr = tid + 256 * k;
+        const int fy = rr % kSide, fx = rr / kSide;
+        const bool in = rr < TR::NF && fx < g.ex && fy < g.ey && g.ez == TS::EZ;
+        f.face[k] = field[in ? base + (uint64_t)fx * sx + (uint64_t)fy * dz + 16 * TZ : base];
+    }
+}
+
+// The fetched tile into LDS (rows outside a partial tile's extent receive
+// values that are never read); a tile that was not fetched loads here.
+template <int TZ>
+__device__ __forceinline__ void tile_place(const TileRegs<TZ> &f, float *__restrict__ v,
+                                           const Job &J, uint64_t base, uint64_t sx, uint64_t dz,
+                                           const Geo &g, int tid)
+{
+    using TS = TileShape<TZ>;
+    using TR = TileRegs<TZ>;
+    if (f.vec) {
+#pragma unroll
+        for (int k = 0; k < TR::IP; k++) {
+            const int i = tid + 256 * k;
+            if (k < TR::IP - 1 || i < TR::NP) {
+                float *p = v + (i / (4 * TZ)) * TS::PZ + 4 * (i % (4 * TZ));
+                p[0] = f.piece[k].x;
+                p[1] = f.piece[k].y;
+                p[2] = f.piece[k].z;
+                p[3] = f.piece[k].w;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TR::IF; k++) {
+            const int rr = tid + 256 * k;
+            if (rr < TR::NF)
+                v[rr * TS::PZ + 16 * TZ] = f.face[k];
+        }
+    } else {
+        lds_fill_tile<TS::NV, TS::PZ, kSide, 4>(v, gmem(J.field), base, sx, dz, 1,
+                                                g.ex == kSide && g.ey == kSide && g.ez == TS::EZ,
+                                                g.ex, g.ey, g.ez);
+        lds_fill_wait();
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Compression: predict + quantize + histogram, persistent over tiles.
+// Compression: predict + quantize + histogram, persistent over tiles. Where
+// the tile fits in registers, the next tile's loads are issued before this
+// tile's levels run, so the levels hide their latency; otherwise each tile
+// is loaded straight into LDS before its levels.
 // ---------------------------------------------------------------------------
 template <int TZ>
 __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs, int njobs,
                                                  uint64_t total, Counters *cnt)
 {
     using TS = TileShape<TZ>;
+    constexpr bool PF = kPrefetchTiles<TZ>;
     __shared__ float v[TS::NV];
     __shared__ __align__(16) uint8_t cb[TS::NC + 16]; // + a dummy slot for faces
     __shared__ uint32_t hist[256];
@@ -994,15 +1121,21 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
     const int t = threadIdx.x;
     hist[t] = 0;
     int cur = -1;
+    // the thread index passes through an empty asm so that index arithmetic
+    // of the unrolled fetches is redone per tile rather than kept in registers
+    int ftid = t;
+    asm volatile("" : "+v"(ftid));
+    TileRegs<TZ> f;
     TileQueue tq = tile_queue(total, cnt);
-    for (int it = 0;; it++) {
-        const uint64_t u = claim_tile(tq, s_tile, it);
-        if (u >= total)
-            break;
+    uint64_t u = claim_tile(tq, s_tile, 0);
+    if (PF && u < total)
+        tile_fetch<TZ>(f, jobs[find_job<WK_TILE>(jobs, njobs, u)], u, ftid);
+    for (int it = 1; u < total; it++) {
+        // every wave is done with the previous tile's LDS past this point
+        const uint64_t un = claim_tile(tq, s_tile, it);
         const int ji = find_job<WK_TILE>(jobs, njobs, u);
         const Job &J = jobs[ji];
         if (ji != cur) {
-            __syncthreads();
             if (cur >= 0) {
                 const uint32_t h = hist[t];
                 if (h)
@@ -1019,10 +1152,14 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
             if (t < kLevels * 3)
                 cfg[t / 3][t % 3] = J.st->cfg[t / 3][t % 3];
             cur = ji;
-            __syncthreads();
+            lds_barrier();
         }
-        if (skip)
+        if (skip) {
+            if (PF && un < total)
+                tile_fetch<TZ>(f, jobs[find_job<WK_TILE>(jobs, njobs, un)], un, ftid);
+            u = un;
             continue;
+        }
         uint64_t ox, oy, oz;
         uint32_t bx, by, bz0;
         const Geo g = tile_geometry<TZ>(J, u - J.tile_begin, ox, oy, oz, bx, by, bz0);
@@ -1031,24 +1168,26 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
         const bool abs_mode = J.mode == 0;
         // a full tile's coarse levels ran ahead on its even-point grid
         const bool coarse = J.crec && g.ex == kSide && g.ey == kSide && g.ez == TS::EZ;
-        CoarseRegs<TZ, 256> cr;
-        int ctid = t;
-        asm volatile("" : "+v"(ctid));
-        if (coarse) {
-            const uint64_t ci = ((uint64_t)bx * J.nf[1] + by) * J.nf[2] + bz0 / TZ;
-            coarse_fetch<TZ, 256>(cr, ctid, gmem(J.crec) + ci * TileShape<TZ, 8>::NV,
-                                  gmem(J.ccode) + ci * TileShape<TZ, 8>::NC);
-        }
         // the tile (with its +1 faces) into LDS
-        lds_fill_tile<TS::NV, TS::PZ, kSide, 4>(v, gmem(J.field), base, sx, dz, 1,
-                                                g.ex == kSide && g.ey == kSide && g.ez == TS::EZ,
-                                                g.ex, g.ey, g.ez);
+        if constexpr (PF) {
+            tile_place<TZ>(f, v, J, base, sx, dz, g, ftid);
+        } else {
+            if (coarse) {
+                const uint64_t ci = ((uint64_t)bx * J.nf[1] + by) * J.nf[2] + bz0 / TZ;
+                coarse_fetch<TZ, 256>(f.cr, ftid, gmem(J.crec) + ci * TileShape<TZ, 8>::NV,
+                                      gmem(J.ccode) + ci * TileShape<TZ, 8>::NC);
+            }
+            lds_fill_tile<TS::NV, TS::PZ, kSide, 4>(v, gmem(J.field), base, sx, dz, 1,
+                                                    g.ex == kSide && g.ey == kSide &&
+                                                        g.ez == TS::EZ,
+                                                    g.ex, g.ey, g.ez);
+            lds_fill_wait();
+        }
         // anchors owned by this tile: local (0, 0, 16j), stored raw from the
         // tile in LDS (the levels never write them)
         if (t < TZ && 16 * t < g.ownz)
             cb[t * 16] = 128;
-        lds_fill_wait();
-        __syncthreads();
+        lds_barrier();
         if (abs_mode) {
             uint32_t kmn = 0xffffffffu, kmx = 0u;
             bool bad = false;
@@ -1060,9 +1199,12 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
                 gstore_u2(gmem(J.mm_part) + (u - J.tile_begin), make_uint2(kmn, kmx));
         }
         if (coarse) {
-            coarse_place<TZ, 256>(cr, ctid, v, cb);
-            __syncthreads();
+            coarse_place<TZ, 256>(f.cr, ftid, v, cb);
+            lds_barrier();
         }
+        // the next tile's loads fly while this tile's levels run
+        if (PF && un < total)
+            tile_fetch<TZ>(f, jobs[find_job<WK_TILE>(jobs, njobs, un)], un, ftid);
         if (t < TZ && 16 * t < g.ownz) {
             const uint64_t ai = ((uint64_t)bx * J.nb[1] + by) * J.nb[2] + bz0 + t;
             const uint64_t off = J.off_anchors + 4 * ai;
@@ -1075,7 +1217,7 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
             walk_levels<TZ, true>(v, cb, nullptr, g, cfg, qp);
         // codes of owned points -> global, histogram in LDS
         if (g.ownz == TS::OZ && (dz & 15) == 0) {
-            for (int i = t; i < 16 * 16 * TZ; i += blockDim.x) {
+            for (int i = t; i < 16 * 16 * TZ; i += 256) {
                 const int w = i % TZ, r = i / TZ;
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
@@ -1092,7 +1234,7 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
                 }
             }
         } else {
-            for (int i = t; i < 16 * 16 * TS::OZ; i += blockDim.x) {
+            for (int i = t; i < 16 * 16 * TS::OZ; i += 256) {
                 const int z = i % TS::OZ, r = i / TS::OZ;
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny && z < g.ownz) {
@@ -1102,7 +1244,7 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
                 }
             }
         }
-        __syncthreads();
+        u = un;
     }
     __syncthreads();
     if (cur >= 0) {
@@ -1183,7 +1325,7 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
         uint32_t bx, by, bz0;
         const Geo g = tile_geometry<TZ>(J, u - J.tile_begin, ox, oy, oz, bx, by, bz0);
         const uint64_t dy = J.dims[1], dz = J.dims[2];
-        for (int r = t; r < TS::NROW; r += blockDim.x) {
+        for (int r = t; r < TS::NROW; r += 256) {
             const int x = r / kSide, y = r % kSide;
             rowoff[r] = ((ox + x) * dy + (oy + y)) * dz + oz;
         }
@@ -1249,7 +1391,7 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
             walk_levels<TZ, false>(v, nullptr, cl, g, cfg, qp);
         }
         if (g.ownz == TS::OZ && (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.out) & 15) == 0) {
-            for (int i = t; i < 16 * 16 * 4 * TZ; i += blockDim.x) {
+            for (int i = t; i < 16 * 16 * 4 * TZ; i += 256) {
                 const int w = i % (4 * TZ), r = i / (4 * TZ);
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
@@ -1259,7 +1401,7 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
                 }
             }
         } else {
-            for (int i = t; i < 16 * 16 * TS::OZ; i += blockDim.x) {
+            for (int i = t; i < 16 * 16 * TS::OZ; i += 256) {
                 const int z = i % TS::OZ, r = i / TS::OZ;
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny && z < g.ownz)
