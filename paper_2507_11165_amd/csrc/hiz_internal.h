@@ -170,6 +170,10 @@ void launch_coarse(const Job *d_jobs, int njobs, uint64_t total, int tile_z, boo
 // Values (4 bytes each) and codes of one tile's even-point grid.
 uint64_t coarse_values_per_tile(int tile_z);
 uint64_t coarse_codes_per_tile(int tile_z);
+// Workspace bound over every shape of n points (a stream's field size before
+// its header is read): hiz_workspace_bound of an n x 1 x 1 field plus the
+// most pre-pass slots any shape of n points can have.
+uint64_t workspace_bound_points(uint64_t n);
 int reconstruct_blocks_per_cu(int tile_z);
 
 // ---- device helpers shared by the kernels ----

@@ -713,6 +713,13 @@ __device__ __forceinline__ Geo tile_geometry(const Job &J, uint64_t lt, uint64_t
     return g;
 }
 
+// Tiles whose owned points all lie inside the field (only a far face may be
+// missing, where the field ends): their coarse levels run in the pre-pass.
+template <int TZ> __device__ __forceinline__ bool prepass_tile(const Geo &g)
+{
+    return g.ownx == 16 && g.owny == 16 && g.ownz == 16 * TZ;
+}
+
 // Tiles handed out on demand. Each XCD (workgroups are dealt to the eight
 // XCDs round-robin by blockIdx) owns a contiguous eighth of the tile list, so
 // tiles that share halo faces meet in the same L2, and its workgroups claim
@@ -751,7 +758,10 @@ __device__ __forceinline__ uint64_t next_tile(TileQueue &q)
         const int x = (q.home + q.k) & 7;
         const uint64_t lo = eighth_lo(q.total, x), hi = eighth_lo(q.total, x + 1);
         if (lo + q.ask < hi) {
-            const uint64_t u = lo + q.ask;
+            // an eighth is dealt from its end: the tiles cut by the field's
+            // far faces (slower: all four levels, general line code) gather
+            // there and go first instead of holding up the end of the launch
+            const uint64_t u = hi - 1 - q.ask;
             q.ask = atomicAdd(&q.ctr[x], 1u);
             return u;
         }
@@ -1023,7 +1033,7 @@ __device__ __forceinline__ void tile_fetch(TileRegs<TZ> &f, const Job &J, uint64
     const bool full = g.ex == kSide && g.ey == kSide && g.ez == TS::EZ;
     f.vec = (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.field) & 15) == 0 &&
             g.ez >= 16 * TZ;
-    if (J.crec && full) {
+    if (J.crec && prepass_tile<TZ>(g)) {
         const uint64_t ci = ((uint64_t)bx * J.nf[1] + by) * J.nf[2] + bz0 / TZ;
         coarse_fetch<TZ, 256>(f.cr, tid, gmem(J.crec) + ci * TileShape<TZ, 8>::NV,
                               gmem(J.ccode) + ci * TileShape<TZ, 8>::NC);
@@ -1166,8 +1176,8 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
         const uint64_t dy = J.dims[1], dz = J.dims[2];
         const uint64_t sx = dy * dz, base = (ox * dy + oy) * dz + oz;
         const bool abs_mode = J.mode == 0;
-        // a full tile's coarse levels ran ahead on its even-point grid
-        const bool coarse = J.crec && g.ex == kSide && g.ey == kSide && g.ez == TS::EZ;
+        // the coarse levels of this tile ran ahead on its even-point grid
+        const bool coarse = J.crec && prepass_tile<TZ>(g);
         // the tile (with its +1 faces) into LDS
         if constexpr (PF) {
             tile_place<TZ>(f, v, J, base, sx, dz, g, ftid);
@@ -1333,7 +1343,7 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
         HIZ_GLOBAL const float *anchors =
             reinterpret_cast<HIZ_GLOBAL const float *>(gmem(J.stream) + J.off_anchors);
         const bool vec = (dz & 15) == 0;
-        const bool coarse = J.crec && g.ex == kSide && g.ey == kSide && g.ez == TS::EZ;
+        const bool coarse = J.crec && prepass_tile<TZ>(g);
         CoarseRegs<TZ, 256> cr;
         int ctid = t;
         asm volatile("" : "+v"(ctid));
@@ -1433,14 +1443,17 @@ void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t total, int tile_z
 }
 
 // ---------------------------------------------------------------------------
-// Coarse levels (strides 8, 4, 2) of every full tile, one wave per tile, on
-// the tile's grid of even points: 9 x 9 x (8 TZ + 1) values, the same
-// computation as in the full tile at half the coordinates (strides 4, 2, 1).
+// Coarse levels (strides 8, 4, 2) of every tile whose owned points all lie in
+// the field, one wave per tile, on the tile's grid of even points: up to
+// 9 x 9 x (8 TZ + 1) values, the same computation as in the full tile at half
+// the coordinates (strides 4, 2, 1); a line's samples exist in the half grid
+// exactly when they exist in the full one.
 // Many tiles per CU are in flight at once, so the serial chain of nine
 // sub-steps per tile overlaps across tiles instead of holding a full tile's
 // LDS. The results (values, and codes of the owned points for compression)
 // go to per-tile workspace slots for k_predict / k_reconstruct to overlay.
-// Partial tiles are left to the full kernels, which run all four levels.
+// Tiles cut short inside their owned points are left to the full kernels,
+// which run all four levels.
 // ---------------------------------------------------------------------------
 template <int TZ, bool COMP>
 __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int njobs,
@@ -1463,8 +1476,12 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
         uint32_t bx, by, bz0;
         const uint64_t lt = u - J.tile_begin;
         const Geo gf = tile_geometry<TZ>(J, lt, ox, oy, oz, bx, by, bz0);
-        if (!(gf.ex == kSide && gf.ey == kSide && gf.ez == 16 * TZ + 1))
+        if (!prepass_tile<TZ>(gf))
             continue;
+        // the even-point grid: extents 8 or 9 per axis (8 TZ or 8 TZ + 1 along
+        // z), every owned point inside
+        const Geo gc = {(gf.ex + 1) / 2, (gf.ey + 1) / 2, (gf.ez + 1) / 2, 8, 8, TC::OZ};
+        const bool cfull = gc.ex == TC::SIDE && gc.ey == TC::SIDE && gc.ez == TC::EZ;
         __syncthreads();
         if (t == 0) {
             qp.eps = st->eps;
@@ -1486,7 +1503,8 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
         if constexpr (COMP) {
             // the even points straight into LDS, all in flight at once
             lds_fill_tile<TC::NV, TC::PZ, TC::SIDE, 1>(v, gmem(J.field), (ox * dy + oy) * dz + oz,
-                                                       2 * dy * dz, 2 * dz, 2, true, 0, 0, 0);
+                                                       2 * dy * dz, 2 * dz, 2, cfull, gc.ex, gc.ey,
+                                                       gc.ez);
             if (t < TZ)
                 cb[8 * t] = 128; // anchors (0, 0, 8j)
         } else {
@@ -1501,7 +1519,10 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
 #pragma unroll
                 for (int k = 0; k < B; k++) {
                     const int i = i0 + tid + 64 * k;
-                    c[k] = codes[gidx(i < TC::NV ? i : 0)];
+                    const int zc = i % TC::PZ, r = i / TC::PZ;
+                    const int yc = r % TC::SIDE, xc = r / TC::SIDE;
+                    const bool in = i < TC::NV && xc < gc.ex && yc < gc.ey && zc < gc.ez;
+                    c[k] = codes[gidx(in ? i : 0)];
                 }
                 float ov[B];
 #pragma unroll
@@ -1509,14 +1530,15 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
                     const int i = i0 + tid + 64 * k;
                     const int zc = i % TC::PZ, r = i / TC::PZ;
                     const int yc = r % TC::SIDE, xc = r / TC::SIDE;
+                    const bool in = i < TC::NV && xc < gc.ex && yc < gc.ey && zc < gc.ez;
                     const bool anchor = (xc & 7) == 0 && (yc & 7) == 0 && (zc & 7) == 0;
                     const uint64_t ai = ((uint64_t)(bx + (xc >> 3)) * J.nb[1] + (by + (yc >> 3))) *
                                             J.nb[2] +
                                         bz0 + (zc >> 3);
                     ov[k] = 0.f;
-                    if (i < TC::NV && anchor)
+                    if (in && anchor)
                         ov[k] = anchors[ai];
-                    else if (i < TC::NV && c[k] == 0)
+                    else if (in && c[k] == 0)
                         ov[k] = out[gidx(i)];
                 }
 #pragma unroll
@@ -1531,7 +1553,6 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
         }
         lds_fill_wait();
         __syncthreads();
-        const Geo gc = {TC::SIDE, TC::SIDE, TC::EZ, 8, 8, TC::OZ};
 #pragma unroll 1
         for (int l = 0; l < kLevels - 1; l++) {
             if constexpr (COMP)

@@ -460,13 +460,14 @@ hiz_status resolve_params(hiz_ctx *c, const hiz_params *params, hiz_params &p, i
     return HIZ_OK;
 }
 
-// Tiles whose blocks all have their +1 face inside the field, per axis: a
-// block starting at 16b is full when 16b + 16 < d.
+// Tiles whose owned points all lie inside the field (their coarse levels run
+// in the pre-pass), per axis: a block starting at 16b qualifies when
+// 16b + 16 <= d.
 void set_full_tiles(Job &J, int tz)
 {
-    J.nf[0] = (uint32_t)((J.dims[0] - 1) / kAnchor);
-    J.nf[1] = (uint32_t)((J.dims[1] - 1) / kAnchor);
-    J.nf[2] = (uint32_t)((J.dims[2] - 1) / kAnchor / (uint64_t)tz);
+    J.nf[0] = (uint32_t)(J.dims[0] / kAnchor);
+    J.nf[1] = (uint32_t)(J.dims[1] / kAnchor);
+    J.nf[2] = (uint32_t)(J.dims[2] / kAnchor / (uint64_t)tz);
 }
 
 uint64_t full_tiles(const Job &J) { return (uint64_t)J.nf[0] * J.nf[1] * J.nf[2]; }
@@ -1163,14 +1164,33 @@ uint64_t hiz_workspace_bound(const uint64_t dims[3])
     // per-tile coarse-level slots (values and codes of the even-point grid)
     uint64_t coarse = 0;
     for (int tz = 1; tz <= 4; tz *= 2) {
-        const uint64_t nt = ((dims[0] - 1) / kAnchor) * ((dims[1] - 1) / kAnchor) *
-                            ((dims[2] - 1) / kAnchor / tz);
+        const uint64_t nt = (dims[0] / kAnchor) * (dims[1] / kAnchor) * (dims[2] / kAnchor / tz);
         coarse = std::max(coarse, nt * (4 * coarse_values_per_tile(tz) + coarse_codes_per_tile(tz)));
     }
     const uint64_t comp = per_job + N + 16 * groups + 16 * chunks + 8 * mm + coarse;
     const uint64_t dec = per_job + sizeof(DecTables) + N + 8 * cdiv(chunks, 256) + coarse;
     return std::max(comp, dec);
 }
+
+} // extern "C"
+
+namespace hiz {
+uint64_t workspace_bound_points(uint64_t n)
+{
+    const uint64_t d[3] = {n, 1, 1};
+    const uint64_t b = hiz_workspace_bound(d);
+    if (b == 0)
+        return 0;
+    // a tile of 16 x 16 x 16 tz owned points has one slot
+    uint64_t coarse = 0;
+    for (int tz = 1; tz <= 4; tz *= 2)
+        coarse = std::max<uint64_t>(coarse, n / (4096ull * tz) * (4 * coarse_values_per_tile(tz) +
+                                                                 coarse_codes_per_tile(tz)));
+    return b + coarse;
+}
+} // namespace hiz
+
+extern "C" {
 
 void hiz_set_profiling(hiz_ctx *c, int on)
 {

@@ -231,24 +231,28 @@ hiz_status hiz_server_submit(hiz_server *S, const hiz_request *r)
     if (!S || !r || (r->op != HIZ_OP_COMPRESS && r->op != HIZ_OP_DECOMPRESS) || !r->d_in ||
         !r->d_out)
         return HIZ_ERR_ARG;
-    uint64_t n_elems;
+    uint64_t need;
     if (r->op == HIZ_OP_COMPRESS) {
-        n_elems = 1;
+        uint64_t n_elems = 1;
         for (int k = 0; k < 3; k++) {
             if (r->dims[k] == 0 || n_elems > (1ull << 40) / r->dims[k])
                 return HIZ_ERR_ARG;
             n_elems *= r->dims[k];
         }
+        need = hiz_workspace_bound(r->dims);
     } else {
-        n_elems = r->out_cap; // the field the stream decodes into bounds its size
-        if (n_elems == 0)
+        // the field the stream decodes into bounds its size; its shape is in
+        // the stream's header on the device, so the bound covers every shape
+        if (r->out_cap == 0)
             return HIZ_ERR_ARG;
+        need = hiz::workspace_bound_points(r->out_cap);
     }
-    const uint64_t d[3] = {n_elems, 1, 1};
+    if (need == 0)
+        return HIZ_ERR_ARG;
     hiz::serve::Req q;
     q.id = r->id;
     q.op = r->op;
-    q.need = hiz_workspace_bound(d);
+    q.need = need;
     {
         std::lock_guard<std::mutex> g(S->dev.args_mu);
         q.payload = S->next_key++;
