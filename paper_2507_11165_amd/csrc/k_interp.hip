@@ -729,7 +729,12 @@ template <int TZ> __device__ __forceinline__ bool prepass_tile(const Geo &g)
 // that holds more partial tiles does not hold up the launch. Thread 0 asks
 // for the next tile while the current one is processed; the index goes
 // through a two-slot LDS buffer so that it never overwrites the one some
-// wave is still reading.
+// wave is still reading. The claims are made by the first lane of the last
+// wave, which issues no global stores of its own: reading a claim's result
+// then waits only for that wave's loads (long done), not for the tile's
+// output stores still draining.
+constexpr int kClaimThread = 192;
+constexpr int kStoreThreads = 192; // threads of a tile's output stores
 struct TileQueue {
     uint64_t total;
     uint32_t *ctr; // eight counters, one per eighth
@@ -746,11 +751,11 @@ __device__ __forceinline__ TileQueue tile_queue(uint64_t total, Counters *cnt)
     q.home = (gridDim.x >= 8 && (gridDim.x & 7) == 0) ? (int)(blockIdx.x & 7) : 0;
     q.k = 0;
     q.ask = 0;
-    if (threadIdx.x == 0)
+    if (threadIdx.x == kClaimThread)
         q.ask = atomicAdd(&q.ctr[q.home], 1u);
     return q;
 }
-// Thread 0: resolve the outstanding claim into a tile index (total = none
+// Claiming thread: resolve the outstanding claim into a tile index (total = none
 // left) and ask for the following one.
 __device__ __forceinline__ uint64_t next_tile(TileQueue &q)
 {
@@ -773,7 +778,7 @@ __device__ __forceinline__ uint64_t next_tile(TileQueue &q)
 }
 __device__ __forceinline__ uint64_t claim_tile(TileQueue &q, uint64_t *slot, int it)
 {
-    if (threadIdx.x == 0)
+    if (threadIdx.x == kClaimThread)
         slot[it & 1] = next_tile(q);
     lds_barrier();
     // the same for every lane: job lookups and job fields go to scalar loads
@@ -1227,7 +1232,7 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
             walk_levels<TZ, true>(v, cb, nullptr, g, cfg, qp);
         // codes of owned points -> global, histogram in LDS
         if (g.ownz == TS::OZ && (dz & 15) == 0) {
-            for (int i = t; i < 16 * 16 * TZ; i += 256) {
+            for (int i = t; t < kStoreThreads && i < 16 * 16 * TZ; i += kStoreThreads) {
                 const int w = i % TZ, r = i / TZ;
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
@@ -1244,7 +1249,7 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
                 }
             }
         } else {
-            for (int i = t; i < 16 * 16 * TS::OZ; i += 256) {
+            for (int i = t; t < kStoreThreads && i < 16 * 16 * TS::OZ; i += kStoreThreads) {
                 const int z = i % TS::OZ, r = i / TS::OZ;
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny && z < g.ownz) {
@@ -1320,7 +1325,7 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
         const int ji = find_job<WK_TILE>(jobs, njobs, u);
         const Job &J = jobs[ji];
         if (ji != cur) {
-            __syncthreads();
+            lds_barrier();
             if (t == 0) {
                 qp.eps = J.st->eps;
                 qp.two_eb = J.st->two_eb;
@@ -1329,7 +1334,7 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
             if (t < kLevels * 3)
                 cfg[t / 3][t % 3] = J.st->cfg[t / 3][t % 3];
             cur = ji;
-            __syncthreads();
+            lds_barrier();
         }
         uint64_t ox, oy, oz;
         uint32_t bx, by, bz0;
@@ -1339,7 +1344,7 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
             const int x = r / kSide, y = r % kSide;
             rowoff[r] = ((ox + x) * dy + (oy + y)) * dz + oz;
         }
-        __syncthreads();
+        lds_barrier();
         HIZ_GLOBAL const float *anchors =
             reinterpret_cast<HIZ_GLOBAL const float *>(gmem(J.stream) + J.off_anchors);
         const bool vec = (dz & 15) == 0;
@@ -1362,7 +1367,7 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
                 v[x * TS::PX + y * TS::PZ + z] = anchors[ai];
             }
         }
-        __syncthreads();
+        lds_barrier();
         // outliers (code 0, anchors excluded): exact values were scattered into
         // the output beforehand; fetched in batches of 8 per thread
         {
@@ -1392,16 +1397,16 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         if (coarse) {
             coarse_place<TZ, 256>(cr, ctid, v, nullptr);
-            __syncthreads();
+            lds_barrier();
             level<TZ, false>(v, nullptr, cl, g, 1, cfg[kLevels - 1], qp);
         } else {
             walk_levels<TZ, false>(v, nullptr, cl, g, cfg, qp);
         }
         if (g.ownz == TS::OZ && (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.out) & 15) == 0) {
-            for (int i = t; i < 16 * 16 * 4 * TZ; i += 256) {
+            for (int i = t; t < kStoreThreads && i < 16 * 16 * 4 * TZ; i += kStoreThreads) {
                 const int w = i % (4 * TZ), r = i / (4 * TZ);
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
@@ -1411,14 +1416,14 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
                 }
             }
         } else {
-            for (int i = t; i < 16 * 16 * TS::OZ; i += 256) {
+            for (int i = t; t < kStoreThreads && i < 16 * 16 * TS::OZ; i += kStoreThreads) {
                 const int z = i % TS::OZ, r = i / TS::OZ;
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny && z < g.ownz)
                     gmem(J.out)[rowoff[x * kSide + y] + z] = v[x * TS::PX + y * TS::PZ + z];
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
