@@ -696,9 +696,11 @@ __device__ __forceinline__ Geo tile_geometry(const Job &J, uint64_t lt, uint64_t
                                              uint64_t &oz, uint32_t &bx, uint32_t &by,
                                              uint32_t &bz0)
 {
-    const uint64_t tz = lt % J.ntz, r = lt / J.ntz;
-    by = (uint32_t)(r % J.nb[1]);
-    bx = (uint32_t)(r / J.nb[1]);
+    // a launch holds fewer than 2^32 tiles: 32-bit division
+    const uint32_t l = (uint32_t)lt;
+    const uint32_t tz = l % J.ntz, r = l / J.ntz;
+    by = r % J.nb[1];
+    bx = r / J.nb[1];
     bz0 = (uint32_t)(tz * TZ);
     ox = (uint64_t)bx * kAnchor;
     oy = (uint64_t)by * kAnchor;

@@ -635,7 +635,8 @@ hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, int tz, T
             T.max_groups = std::max(T.max_groups, J.n_groups);
         }
     }
-    if (T.groups > 0xffffffffull || T.dblk > 0xffffffffull || T.tune > 0xffffffffull)
+    if (T.groups > 0xffffffffull || T.dblk > 0xffffffffull || T.tune > 0xffffffffull ||
+        T.tiles > 0xffffffffull)
         return fail(c, HIZ_ERR_ARG, "batch too large for one launch");
     hiz_status rc = ensure_ws(c, A.off);
     if (rc)
