@@ -860,82 +860,33 @@ __device__ __forceinline__ void scan_tile_values(const float *__restrict__ v, co
     }
 }
 
-// Codes of the whole tile region (with faces) into LDS.
+// Codes of the whole tile region (with faces) into LDS, any alignment: each
+// thread issues 8 byte loads before it writes any of them.
 template <int TZ>
 __device__ __forceinline__ void load_tile_codes(uint8_t *__restrict__ cl,
                                                 HIZ_GLOBAL const uint8_t *__restrict__ codes,
-                                                const uint64_t *rowoff, const Geo &g, bool vec)
+                                                uint64_t base, uint64_t sx, uint64_t dz,
+                                                const Geo &g)
 {
     using TS = TileShape<TZ>;
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    if (vec) {
-        constexpr int PIECES = TZ + 1; // TZ 16-byte pieces and the face byte
-        constexpr int ITEMS = TS::NROW * PIECES;
-        constexpr int BATCH = (ITEMS + 255) / 256 < 8 ? (ITEMS + 255) / 256 : 8;
 #pragma nounroll
-        for (int i0 = 0; i0 < ITEMS; i0 += 256 * BATCH) {
-            uint4 buf[BATCH];
-            uint32_t face[BATCH];
+    for (int i0 = 0; i0 < TS::NV; i0 += 256 * 8) {
+        uint8_t b[8];
 #pragma unroll
-            for (int k = 0; k < BATCH; k++) {
-                const int i = i0 + tid + 256 * k;
-                const int r = i / PIECES, pc = i - r * PIECES;
-                const int y = r % kSide, x = r / kSide;
-                buf[k] = make_uint4(0, 0, 0, 0);
-                face[k] = 0;
-                const bool row = i < ITEMS && x < g.ex && y < g.ey;
-                HIZ_GLOBAL const uint8_t *rp = codes + rowoff[row ? r : 0];
-                if (row && pc < TZ && 16 * pc + 16 <= g.ez)
-                    buf[k] = gload_u4(rp + 16 * pc);
-                if (row && pc == TZ && 16 * pc < g.ez)
-                    face[k] = rp[16 * pc];
-            }
-#pragma unroll
-            for (int k = 0; k < BATCH; k++) {
-                const int i = i0 + tid + 256 * k;
-                const int r = i / PIECES, pc = i - r * PIECES;
-                const int y = r % kSide, x = r / kSide;
-                if (i < ITEMS && x < g.ex && y < g.ey) {
-                    uint8_t *cp = cl + x * TS::PX + y * TS::PZ + 16 * pc;
-                    const int z0 = 16 * pc;
-                    if (pc < TZ && z0 + 16 <= g.ez) {
-                        const uint32_t w[4] = {buf[k].x, buf[k].y, buf[k].z, buf[k].w};
-#pragma unroll
-                        for (int j = 0; j < 16; j++)
-                            cp[j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
-                    } else if (pc < TZ) {
-                        // a row cut short by the field boundary (rare)
-                        for (int z = z0; z < g.ez; z++)
-                            cp[z - z0] = codes[rowoff[r] + z];
-                    } else if (z0 < g.ez) {
-                        cp[0] = (uint8_t)face[k];
-                    }
-                }
-            }
+        for (int k = 0; k < 8; k++) {
+            const int e = i0 + tid + 256 * k;
+            const int z = e % TS::PZ, r = e / TS::PZ;
+            const int y = r % kSide, x = r / kSide;
+            const bool in = e < TS::NV && x < g.ex && y < g.ey && z < g.ez;
+            b[k] = codes[in ? base + (uint64_t)x * sx + (uint64_t)y * dz + z : base];
         }
-    } else {
-        constexpr int NE = TS::NROW * TS::EZ;
-#pragma nounroll
-        for (int i0 = 0; i0 < NE; i0 += 256 * 8) {
-            uint8_t b[8];
 #pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const int i = i0 + threadIdx.x + 256 * k;
-                const int z = i % TS::EZ, r = i / TS::EZ;
-                const int y = r % kSide, x = r / kSide;
-                b[k] = 0;
-                if (i < NE && x < g.ex && y < g.ey && z < g.ez)
-                    b[k] = codes[rowoff[r] + z];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const int i = i0 + threadIdx.x + 256 * k;
-                const int z = i % TS::EZ, r = i / TS::EZ;
-                const int y = r % kSide, x = r / kSide;
-                if (i < NE && x < g.ex && y < g.ey && z < g.ez)
-                    cl[x * TS::PX + y * TS::PZ + z] = b[k];
-            }
+        for (int k = 0; k < 8; k++) {
+            const int e = i0 + tid + 256 * k;
+            if (e < TS::NV)
+                cl[e] = b[k];
         }
     }
 }
@@ -1302,8 +1253,140 @@ int predict_blocks_per_cu(int tile_z)
     return n > 0 ? n : 1;
 }
 
+// A tile's codes (and anchors, and for a pre-pass tile its coarse-grid
+// values) fetched into registers while the previous tile is reconstructed:
+// rows of the tile as 16-byte pieces (thread t holds pieces t + 256 k, a piece
+// being 16 consecutive z of one (x, y) row) and the far z face one code per
+// row. Needs rows that start 16-byte aligned (dz a multiple of 16) and tiles
+// that hold every piece; other tiles load their codes when placed.
+template <int TZ> struct CodeRegs {
+    static constexpr int NP = kSide * kSide * TZ; // pieces
+    static constexpr int IP = (NP + 255) / 256;
+    static constexpr int NF = kSide * kSide;
+    static constexpr int IF = (NF + 255) / 256;
+    static constexpr int NA = 4 * (TZ + 1); // anchors of the tile region
+    uint4 piece[IP];
+    uint32_t face[IF];
+    float anchor;
+    CoarseRegs<TZ, 256> cr;
+    bool vec;
+};
+
+// whether a 32-bit word holds a zero byte
+__device__ __forceinline__ bool has_zero_byte(uint32_t w)
+{
+    return ((w - 0x01010101u) & ~w & 0x80808080u) != 0;
+}
+
+template <int TZ>
+__device__ __forceinline__ void code_fetch(CodeRegs<TZ> &f, const Job &J, uint64_t u, int tid)
+{
+    using TS = TileShape<TZ>;
+    using CR = CodeRegs<TZ>;
+    // opaque per tile: the unrolled index arithmetic is not hoisted out of the
+    // tile loop into long-lived registers
+    asm volatile("" : "+v"(tid));
+    uint64_t ox, oy, oz;
+    uint32_t bx, by, bz0;
+    const Geo g = tile_geometry<TZ>(J, u - J.tile_begin, ox, oy, oz, bx, by, bz0);
+    const uint64_t dy = J.dims[1], dz = J.dims[2];
+    const uint64_t sx = dy * dz, base = (ox * dy + oy) * dz + oz;
+    const bool full = g.ex == kSide && g.ey == kSide && g.ez == TS::EZ;
+    if (J.crec && prepass_tile<TZ>(g)) {
+        const uint64_t ci = ((uint64_t)bx * J.nf[1] + by) * J.nf[2] + bz0 / TZ;
+        coarse_fetch<TZ, 256>(f.cr, tid, gmem(J.crec) + ci * TileShape<TZ, 8>::NV, nullptr);
+    }
+    // anchors of the tile region: every coordinate a multiple of 16
+    {
+        const int x = 16 * (tid & 1), y = 16 * ((tid >> 1) & 1), z = 16 * (tid >> 2);
+        const bool in = tid < CR::NA && x < g.ex && y < g.ey && z < g.ez;
+        const uint64_t ai = ((uint64_t)(bx + (x >> 4)) * J.nb[1] + (by + (y >> 4))) * J.nb[2] +
+                            bz0 + (z >> 4);
+        HIZ_GLOBAL const float *anchors =
+            reinterpret_cast<HIZ_GLOBAL const float *>(gmem(J.stream) + J.off_anchors);
+        f.anchor = anchors[in ? ai : 0];
+    }
+    f.vec = (dz & 15) == 0 && g.ez >= 16 * TZ;
+    if (!f.vec)
+        return;
+    HIZ_GLOBAL const uint8_t *codes = gmem(J.codes);
+    // piece t + 256 k: row r = t / TZ + k * 256 / TZ, z = 16 * (t % TZ)
+    constexpr int RS = 256 / TZ, DX = RS / kSide, DY = RS % kSide;
+    int r = tid / TZ;
+    int y = r % kSide, x = r / kSide;
+    uint64_t off = base + (uint64_t)x * sx + (uint64_t)y * dz + 16 * (tid % TZ);
+    const uint64_t d0 = DX * sx + DY * dz, dyw = sx - kSide * dz;
+#pragma unroll
+    for (int k = 0; k < CR::IP; k++) {
+        const bool in = (k < CR::IP - 1 || tid + 256 * k < CR::NP) &&
+                        (full || (x < g.ex && y < g.ey));
+        f.piece[k] = gload_u4(codes + (in ? off : base));
+        x += DX;
+        y += DY;
+        off += d0;
+        if (y >= kSide) {
+            y -= kSide;
+            x += 1;
+            off += dyw;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CR::IF; k++) {
+        const int rr = tid + 256 * k;
+        const int fy = rr % kSide, fx = rr / kSide;
+        const bool in = rr < CR::NF && fx < g.ex && fy < g.ey && g.ez == TS::EZ;
+        f.face[k] = codes[in ? base + (uint64_t)fx * sx + (uint64_t)fy * dz + 16 * TZ : base];
+    }
+}
+
+// The fetched codes into LDS and the anchors into the value tile; returns
+// whether this thread saw a zero code (a possible outlier). A tile that was
+// not fetched loads its codes here.
+template <int TZ>
+__device__ __forceinline__ bool code_place(const CodeRegs<TZ> &f, uint8_t *__restrict__ cl,
+                                           float *__restrict__ v, const Job &J, uint64_t base,
+                                           uint64_t sx, uint64_t dz, const Geo &g, int tid)
+{
+    using TS = TileShape<TZ>;
+    using CR = CodeRegs<TZ>;
+    if (tid < CR::NA) {
+        const int x = 16 * (tid & 1), y = 16 * ((tid >> 1) & 1), z = 16 * (tid >> 2);
+        if (x < g.ex && y < g.ey && z < g.ez)
+            v[x * TS::PX + y * TS::PZ + z] = f.anchor;
+    }
+    if (!f.vec) {
+        load_tile_codes<TZ>(cl, gmem(J.codes), base, sx, dz, g);
+        return true;
+    }
+    bool zero = false;
+#pragma unroll
+    for (int k = 0; k < CR::IP; k++) {
+        const int i = tid + 256 * k;
+        if (k < CR::IP - 1 || i < CR::NP) {
+            uint8_t *p = cl + (i / TZ) * TS::PZ + 16 * (i % TZ);
+            const uint32_t w[4] = {f.piece[k].x, f.piece[k].y, f.piece[k].z, f.piece[k].w};
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                p[j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+            zero |= has_zero_byte(w[0]) | has_zero_byte(w[1]) | has_zero_byte(w[2]) |
+                    has_zero_byte(w[3]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CR::IF; k++) {
+        const int rr = tid + 256 * k;
+        if (rr < CR::NF) {
+            cl[rr * TS::PZ + 16 * TZ] = (uint8_t)f.face[k];
+            zero |= (f.face[k] & 255u) == 0;
+        }
+    }
+    return zero;
+}
+
 // ---------------------------------------------------------------------------
-// Decompression: rebuild the tile from codes, anchors and outliers.
+// Decompression: rebuild the tile from codes, anchors and outliers,
+// persistent over tiles; the next tile's codes are fetched into registers
+// before this tile's levels run, so the levels hide their latency.
 // ---------------------------------------------------------------------------
 template <int TZ>
 __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ jobs, int njobs,
@@ -1312,22 +1395,26 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
     using TS = TileShape<TZ>;
     __shared__ float v[TS::NV];
     __shared__ uint8_t cl[TS::NV];
-    __shared__ uint64_t rowoff[TS::NROW];
     __shared__ uint8_t cfg[kLevels][3];
     __shared__ QParams qp;
     __shared__ uint64_t s_tile[2];
+    __shared__ uint32_t s_zero;
 
     const int t = threadIdx.x;
     int cur = -1;
+    int ftid = t;
+    asm volatile("" : "+v"(ftid));
+    CodeRegs<TZ> f;
     TileQueue tq = tile_queue(total, cnt);
-    for (int it = 0;; it++) {
-        const uint64_t u = claim_tile(tq, s_tile, it);
-        if (u >= total)
-            break;
+    uint64_t u = claim_tile(tq, s_tile, 0);
+    if (u < total)
+        code_fetch<TZ>(f, jobs[find_job<WK_TILE>(jobs, njobs, u)], u, ftid);
+    for (int it = 1; u < total; it++) {
+        // every wave is done with the previous tile's LDS past this point
+        const uint64_t un = claim_tile(tq, s_tile, it);
         const int ji = find_job<WK_TILE>(jobs, njobs, u);
         const Job &J = jobs[ji];
         if (ji != cur) {
-            lds_barrier();
             if (t == 0) {
                 qp.eps = J.st->eps;
                 qp.two_eb = J.st->two_eb;
@@ -1336,84 +1423,64 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
             if (t < kLevels * 3)
                 cfg[t / 3][t % 3] = J.st->cfg[t / 3][t % 3];
             cur = ji;
-            lds_barrier();
         }
+        if (t == 0)
+            s_zero = 0;
         uint64_t ox, oy, oz;
         uint32_t bx, by, bz0;
         const Geo g = tile_geometry<TZ>(J, u - J.tile_begin, ox, oy, oz, bx, by, bz0);
         const uint64_t dy = J.dims[1], dz = J.dims[2];
-        for (int r = t; r < TS::NROW; r += 256) {
-            const int x = r / kSide, y = r % kSide;
-            rowoff[r] = ((ox + x) * dy + (oy + y)) * dz + oz;
-        }
-        lds_barrier();
-        HIZ_GLOBAL const float *anchors =
-            reinterpret_cast<HIZ_GLOBAL const float *>(gmem(J.stream) + J.off_anchors);
-        const bool vec = (dz & 15) == 0;
+        const uint64_t sx = dy * dz, base = (ox * dy + oy) * dz + oz;
         const bool coarse = J.crec && prepass_tile<TZ>(g);
-        CoarseRegs<TZ, 256> cr;
-        int ctid = t;
-        asm volatile("" : "+v"(ctid));
-        if (coarse) {
-            const uint64_t ci = ((uint64_t)bx * J.nf[1] + by) * J.nf[2] + bz0 / TZ;
-            coarse_fetch<TZ, 256>(cr, ctid, gmem(J.crec) + ci * TileShape<TZ, 8>::NV, nullptr);
-        }
-        load_tile_codes<TZ>(cl, gmem(J.codes), rowoff, g, vec);
-        // anchors of the tile region: every coordinate a multiple of 16
-        if (t < 4 * (TZ + 1)) {
-            const int x = 16 * (t & 1), y = 16 * ((t >> 1) & 1), z = 16 * (t >> 2);
-            if (x < g.ex && y < g.ey && z < g.ez) {
-                const uint64_t ai = ((uint64_t)(bx + (x >> 4)) * J.nb[1] + (by + (y >> 4))) *
-                                        J.nb[2] +
-                                    bz0 + (z >> 4);
-                v[x * TS::PX + y * TS::PZ + z] = anchors[ai];
-            }
-        }
         lds_barrier();
-        // outliers (code 0, anchors excluded): exact values were scattered into
-        // the output beforehand; fetched in batches of 8 per thread
-        {
-            constexpr int NE = TS::NROW * TS::EZ;
-    #pragma nounroll
-        for (int i0 = 0; i0 < NE; i0 += 256 * 8) {
+        const bool zero = code_place<TZ>(f, cl, v, J, base, sx, dz, g, ftid);
+        if (__any(zero) && (t & 63) == 0)
+            s_zero = 1;
+        lds_barrier();
+        // outliers (code 0, anchors excluded): their exact values were
+        // scattered into the output beforehand; only tiles holding a zero code
+        // look, 8 loads per thread in flight
+        if (s_zero) {
+            constexpr int NE = TS::NV;
+#pragma nounroll
+            for (int i0 = 0; i0 < NE; i0 += 256 * 8) {
                 float ov[8];
                 bool hit[8];
 #pragma unroll
                 for (int k = 0; k < 8; k++) {
-                    const int i = i0 + t + 256 * k;
-                    const int z = i % TS::EZ, r = i / TS::EZ;
+                    const int e = i0 + t + 256 * k;
+                    const int z = e % TS::PZ, r = e / TS::PZ;
                     const int y = r % kSide, x = r / kSide;
-                    hit[k] = i < NE && x < g.ex && y < g.ey && z < g.ez &&
-                             cl[x * TS::PX + y * TS::PZ + z] == 0 &&
+                    hit[k] = e < NE && x < g.ex && y < g.ey && z < g.ez && cl[e] == 0 &&
                              !((x & 15) == 0 && (y & 15) == 0 && (z & 15) == 0);
-                    ov[k] = hit[k] ? gmem(J.out)[rowoff[r] + z] : 0.f;
+                    ov[k] = hit[k] ? gmem(J.out)[base + (uint64_t)x * sx + (uint64_t)y * dz + z]
+                                   : 0.f;
                 }
 #pragma unroll
-                for (int k = 0; k < 8; k++) {
-                    if (hit[k]) {
-                        const int i = i0 + t + 256 * k;
-                        const int z = i % TS::EZ, r = i / TS::EZ;
-                        const int y = r % kSide, x = r / kSide;
-                        v[x * TS::PX + y * TS::PZ + z] = ov[k];
-                    }
-                }
+                for (int k = 0; k < 8; k++)
+                    if (hit[k])
+                        v[i0 + t + 256 * k] = ov[k];
             }
-        }
-        lds_barrier();
-        if (coarse) {
-            coarse_place<TZ, 256>(cr, ctid, v, nullptr);
             lds_barrier();
-            level<TZ, false>(v, nullptr, cl, g, 1, cfg[kLevels - 1], qp);
-        } else {
-            walk_levels<TZ, false>(v, nullptr, cl, g, cfg, qp);
         }
+        if (coarse) {
+            coarse_place<TZ, 256>(f.cr, ftid, v, nullptr);
+            lds_barrier();
+        }
+        // the next tile's loads fly while this tile's levels run
+        if (un < total)
+            code_fetch<TZ>(f, jobs[find_job<WK_TILE>(jobs, njobs, un)], un, ftid);
+        if (coarse)
+            level<TZ, false>(v, nullptr, cl, g, 1, cfg[kLevels - 1], qp);
+        else
+            walk_levels<TZ, false>(v, nullptr, cl, g, cfg, qp);
         if (g.ownz == TS::OZ && (dz & 3) == 0 && (reinterpret_cast<uintptr_t>(J.out) & 15) == 0) {
             for (int i = t; t < kStoreThreads && i < 16 * 16 * 4 * TZ; i += kStoreThreads) {
                 const int w = i % (4 * TZ), r = i / (4 * TZ);
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
                     const float *vp = v + x * TS::PX + y * TS::PZ + 4 * w;
-                    gstore_f4(gmem(J.out) + rowoff[x * kSide + y] + 4 * w,
+                    gstore_f4(gmem(J.out) + base + (uint64_t)x * sx + (uint64_t)y * dz + 4 * w,
                               make_float4(vp[0], vp[1], vp[2], vp[3]));
                 }
             }
@@ -1422,10 +1489,11 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
                 const int z = i % TS::OZ, r = i / TS::OZ;
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny && z < g.ownz)
-                    gmem(J.out)[rowoff[x * kSide + y] + z] = v[x * TS::PX + y * TS::PZ + z];
+                    gmem(J.out)[base + (uint64_t)x * sx + (uint64_t)y * dz + z] =
+                        v[x * TS::PX + y * TS::PZ + z];
             }
         }
-        lds_barrier();
+        u = un;
     }
 }
 
