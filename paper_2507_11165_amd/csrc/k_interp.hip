@@ -1542,7 +1542,11 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
     __shared__ uint8_t cfg[kLevels][3];
     __shared__ QParams qp;
     const int t = threadIdx.x;
-    for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    // tiles from the end of the list first: those cut by the field's far
+    // faces (slower, general line code) gather there and start early rather
+    // than form the launch's tail
+    for (uint64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const uint64_t u = total - 1 - w;
         const Job &J = jobs[find_job<WK_TILE>(jobs, njobs, u)];
         const FieldState *st = J.st;
         if (COMP && (st->flags & (ST_CONST | ST_NONFINITE)))
