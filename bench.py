@@ -55,9 +55,10 @@ def algorithmic_bytes(name, N, info, n_anchors, shape, tile_z):
     pw = info["payload_words"]
     nch = info["n_chunks"]
     ib = 4 if N < 2 ** 32 else 8
-    # the coarse pre-pass: per full tile, the even-point grid's values read
-    # and written back, plus (compression) the owned even points' codes
-    nf = ((shape[0] - 1) // 16) * ((shape[1] - 1) // 16) * ((shape[2] - 1) // 16 // tile_z)
+    # the coarse pre-pass: per tile whose owned points all lie in the field,
+    # the even-point grid's values read and written back, plus (compression)
+    # the owned even points' codes
+    nf = (shape[0] // 16) * (shape[1] // 16) * (shape[2] // 16 // tile_z)
     nv = 9 * 9 * (8 * tile_z + 1)
     nc = 8 * 8 * 8 * tile_z
     table = {
