@@ -81,10 +81,17 @@ __global__ __launch_bounds__(256) void k_minmax(const Job *__restrict__ jobs, in
         bool bad = false;
         const bool vec = ((reinterpret_cast<uintptr_t>(f) & 15u) == 0) && (hi - lo == kMmUnit);
         if (vec) {
+            // all 16 loads of a thread in flight before any is used: one
+            // memory round trip per unit
             HIZ_GLOBAL const float *fb = f + lo;
-#pragma unroll 4
-            for (int k = 0; k < (int)(kMmUnit / 4 / 256); k++) {
-                const float4 q = gload_f4(fb + 4 * (k * 256 + t));
+            constexpr int K = (int)(kMmUnit / 4 / 256);
+            float4 q4[K];
+#pragma unroll
+            for (int k = 0; k < K; k++)
+                q4[k] = gload_f4(fb + 4 * (k * 256 + t));
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const float4 q = q4[k];
                 float e[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
