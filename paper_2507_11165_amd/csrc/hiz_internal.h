@@ -42,7 +42,7 @@ enum : uint32_t {
 // Decoder lookup tables of one field, built once per decompression.
 constexpr int kLutBits = 13;
 struct DecTables {
-    uint16_t lut[1 << kLutBits]; // (len << 8) | symbol for codes up to kLutBits bits; 0 = slow path
+    uint16_t lut[1 << kLutBits]; // (symbol << 8) | (32 - len) for codes up to kLutBits bits; 0 = slow path
     uint32_t first[kMaxCodeLen + 2]; // first canonical code of each length
     uint32_t count[kMaxCodeLen + 2]; // codes of each length
     uint32_t index[kMaxCodeLen + 2]; // position of the first code of each length in `sorted`

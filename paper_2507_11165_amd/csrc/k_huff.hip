@@ -746,7 +746,7 @@ __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs
         for (int b = 1; b <= kLutBits; b++) {
             const uint32_t c = e >> (kLutBits - b);
             if (blc[b] && c - first[b] < blc[b]) {
-                v = (uint16_t)((b << 8) | s_sorted[index[b] + (c - first[b])]);
+                v = (uint16_t)(((uint32_t)s_sorted[index[b] + (c - first[b])] << 8) | (32u - b));
                 break;
             }
         }
@@ -858,22 +858,28 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     uint64_t pre_base = 0; // payload index of pre[0]
     bool pending = false;
 #pragma unroll
-    for (int j = 0; j < 16; j++)
-        pre[j] = word(wfetch + j);
+    for (int h = 0; h < 2; h++) {
 #pragma unroll
-    for (int j = 0; j < 16; j++)
-        ring[j] = pre[j];
-    wfetch += 16;
-    wp = 16;
-    uint64_t buf = 0;
-    int nb = 0;
+        for (int j = 0; j < 16; j++)
+            pre[j] = word(wfetch + j);
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            ring[16 * h + j] = pre[j];
+        wfetch += 16;
+    }
+    wp = 32;
     uint64_t used = 0;
     uint32_t zeros = 0;
     bool bad = false;
-    // the next ring word waits in a register, so a refill of the bit buffer
-    // never waits for LDS; rp counts words taken out of the ring
-    uint32_t nextw = ring[0];
-    rp = 1;
+    // Bit buffer: the next nb (33..64 before a symbol) payload bits, first
+    // bit at the top of hi, then lo; zeros below them. idx is the table index
+    // of the next code (its first kLutBits bits). The word after the buffer
+    // waits in nextw, so a refill never waits for LDS; rp counts words taken
+    // out of the ring.
+    uint32_t hi = ring[0], lo = ring[1], nextw = ring[2];
+    rp = 3;
+    int nb = 64;
+    uint32_t e = lut[hi >> (32 - kLutBits)];
     const uint32_t nblk = (nsym + 15) >> 4;
 #pragma nounroll
     for (uint32_t blk = 0; blk < nblk; blk++) {
@@ -914,23 +920,49 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         }
         uint32_t out[4] = {0u, 0u, 0u, 0u};
         const uint32_t nk = min(16u, nsym - (blk << 4));
-        // one symbol: refill the bit buffer without a branch (the ring word
-        // after nextw is read every time, used when a refill happens), look
-        // up the code, and consume it; only codes longer than the table
-        // branch off
-        auto step = [&](int k, bool active) {
-            const bool need = nb < 32;
-            const uint32_t nw = ring[rp & (kRing - 1)];
-            buf |= (uint64_t)(need ? nextw : 0u) << (need ? 32 - nb : 0);
+        // one symbol. After a code is taken off the buffer, nb <= 32 asks for
+        // the next word: it goes in below the valid bits by selects (the ring
+        // word after nextw is read every time), no branch. A table hit (codes
+        // up to kLutBits bits) leaves at least 20 valid bits, so the next
+        // index comes from the shifted buffer before the refill, and the
+        // chain from one table read to the next is three operations. Longer
+        // codes take the search by length, then refill, then index.
+        auto refill = [&](uint32_t nw) {
+            const bool need = nb <= 32;
+            const uint64_t add = ((uint64_t)nextw << 32) >> (need ? nb : 0);
+            hi |= need ? (uint32_t)(add >> 32) : 0u;
+            lo |= need ? (uint32_t)add : 0u;
             nb += need ? 32 : 0;
             nextw = need ? nw : nextw;
             rp += need ? 1u : 0u;
-            const uint32_t e = lut[buf >> (64 - kLutBits)];
-            uint32_t L = e >> 8, sym = e & 255u;
-            if (e == 0) {
+        };
+        auto step = [&](int k, bool active) {
+            if (!active)
+                return;
+            // e, the table entry of the code at the buffer's top, was read a
+            // step ahead: (symbol << 8) | (32 - length), 0 for a longer code
+            const uint32_t nw = ring[rp & (kRing - 1)];
+            const uint32_t hi0 = hi, lo0 = lo, nextw0 = nextw, rp0 = rp;
+            const int nb0 = nb;
+            const uint32_t sh = e & 255u;
+            uint32_t L = 32 - sh, sym = e >> 8;
+            const uint32_t nhi = __builtin_amdgcn_alignbit(hi, lo, sh);
+            // the next entry, before anything else: a table hit leaves at
+            // least 20 valid bits, so the refill below cannot change it
+            uint32_t en = lut[nhi >> (32 - kLutBits)];
+            hi = nhi;
+            lo <<= (L & 31u);
+            nb -= (int)L;
+            refill(nw);
+            // a code longer than the table (rare): search by length from the
+            // saved state, then refill and read the next entry again; the
+            // wave-uniform test keeps the common path free of exec masking
+            // and the volatile read keeps the two entry reads apart
+            if (__builtin_expect(__any(e == 0), 0) && e == 0) {
+                uint64_t b64 = ((uint64_t)hi0 << 32) | lo0;
                 sym = 0;
                 for (L = kLutBits + 1; L <= maxlen; L++) {
-                    const uint32_t c = (uint32_t)(buf >> (64 - L));
+                    const uint32_t c = (uint32_t)(b64 >> (64 - L));
                     if (c - first[L] < count[L]) {
                         sym = sorted[index[L] + (c - first[L])];
                         break;
@@ -940,14 +972,19 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
                     bad = true;
                     L = 1;
                 }
+                b64 <<= L;
+                hi = (uint32_t)(b64 >> 32);
+                lo = (uint32_t)b64;
+                nb = nb0 - (int)L;
+                nextw = nextw0;
+                rp = rp0;
+                refill(nw);
+                en = reinterpret_cast<volatile const uint16_t *>(lut)[hi >> (32 - kLutBits)];
             }
-            if (active) {
-                buf <<= L;
-                nb -= (int)L;
-                used += L;
-                zeros += (sym == 0);
-                out[k >> 2] |= sym << (8 * (k & 3));
-            }
+            e = en;
+            used += L;
+            zeros += (sym == 0);
+            out[k >> 2] |= sym << (8 * (k & 3));
         };
         if (nk == 16) {
 #pragma unroll
