@@ -774,7 +774,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     __shared__ uint32_t s_id, s_maxlen;
     __shared__ uint64_t s_wsum[4];
     __shared__ uint64_t s_base;
-    __shared__ uint32_t s_win[kDecChunks * (kRing + 1)];
+    __shared__ uint32_t s_win[kDecChunks * kRing];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (t == 0)
         s_id = atomicAdd(&cnt->dec_next, 1u);
@@ -845,7 +845,10 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     // 32 bits), so the ring holding 16 words at a block's start is enough; a
     // lane below that (codes far longer than usual) refills synchronously.
     // Words past the chunk's end read as zero.
-    uint32_t *ring = s_win + t * (kRing + 1);
+    // slot i of this lane's ring is s_win[i * kDecChunks + t]: the lanes of
+    // a wave touch consecutive words whatever slots they are at (no bank
+    // conflicts)
+    uint32_t *ring = s_win + t;
     // payload word idx of this chunk, 0 past its end; the load itself is never
     // skipped (its index is clamped inside the payload), so a run of them is
     // issued back to back without a branch or a wait between them
@@ -864,7 +867,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
             pre[j] = word(wfetch + j);
 #pragma unroll
         for (int j = 0; j < 16; j++)
-            ring[16 * h + j] = pre[j];
+            ring[(16 * h + j) * kDecChunks] = pre[j];
         wfetch += 16;
     }
     wp = 32;
@@ -876,7 +879,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     // of the next code (its first kLutBits bits). The word after the buffer
     // waits in nextw, so a refill never waits for LDS; rp counts words taken
     // out of the ring.
-    uint32_t hi = ring[0], lo = ring[1], nextw = ring[2];
+    uint32_t hi = ring[0], lo = ring[kDecChunks], nextw = ring[2 * kDecChunks];
     rp = 3;
     int nb = 64;
     uint32_t e = lut[hi >> (32 - kLutBits)];
@@ -887,7 +890,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         if (pending) {
 #pragma unroll
             for (int j = 0; j < 16; j++)
-                ring[(wp + j) & (kRing - 1)] = pre_base + j < wend ? pre[j] : 0u;
+                ring[((wp + j) & (kRing - 1)) * kDecChunks] = pre_base + j < wend ? pre[j] : 0u;
             wp += 16;
             pending = false;
         }
@@ -899,7 +902,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
                 r[j] = word(wfetch + j);
 #pragma unroll
             for (int j = 0; j < 16; j++)
-                ring[(wp + j) & (kRing - 1)] = r[j];
+                ring[((wp + j) & (kRing - 1)) * kDecChunks] = r[j];
             wfetch += 16;
             wp += 16;
         }
@@ -941,7 +944,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
                 return;
             // e, the table entry of the code at the buffer's top, was read a
             // step ahead: (symbol << 8) | (32 - length), 0 for a longer code
-            const uint32_t nw = ring[rp & (kRing - 1)];
+            const uint32_t nw = ring[(rp & (kRing - 1)) * kDecChunks];
             const uint32_t hi0 = hi, lo0 = lo, nextw0 = nextw, rp0 = rp;
             const int nb0 = nb;
             const uint32_t sh = e & 255u;
