@@ -79,6 +79,22 @@ def test_every_scheme(ctx, ci):
     check_case(ctx, x, O.REL, 1e-3, tune=False, cfg=CFGS[ci], chunk=1024, tile_z=1 + ci % 2)
 
 
+# Dimensions that are multiples of 16 leave the last block along an axis
+# without its +1 face: those tiles still run their coarse levels in the
+# pre-pass (on a half grid cut short by the field), with every scheme.
+@pytest.mark.parametrize("tile_z", [1, 2, 4])
+@pytest.mark.parametrize("shape", [(64, 48, 96), (48, 64, 33), (32, 33, 128)])
+def test_tiles_without_far_faces(ctx, shape, tile_z):
+    x = G.grf(shape, 3.0, 31 + shape[2] + tile_z)
+    check_case(ctx, x, O.REL, 1e-3, tune=True, chunk=512, tile_z=tile_z)
+
+
+@pytest.mark.parametrize("ci", [0, 3, 4, 6])
+def test_tiles_without_far_faces_every_scheme(ctx, ci):
+    x = G.grf((48, 32, 64), 2.5, 41 + ci)
+    check_case(ctx, x, O.REL, 1e-3, tune=False, cfg=CFGS[ci], chunk=256, tile_z=2)
+
+
 @pytest.mark.parametrize("seed", range(16))
 def test_random_shapes(ctx, seed):
     rng = np.random.default_rng(500 + seed)
