@@ -304,10 +304,20 @@ __device__ inline void reduce_partials(const uint2 *p, uint64_t n, uint32_t &kmn
 {
     kmn = 0xffffffffu;
     kmx = 0u;
-    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint2 v = p[i];
-        kmn = min(kmn, v.x);
-        kmx = max(kmx, v.y);
+    // 8 loads per thread in flight per round trip
+    const uint64_t step = blockDim.x;
+    for (uint64_t i0 = threadIdx.x; i0 < n; i0 += 8 * step) {
+        uint2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint64_t i = i0 + k * step;
+            v[k] = i < n ? p[i] : make_uint2(0xffffffffu, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            kmn = min(kmn, v[k].x);
+            kmx = max(kmx, v[k].y);
+        }
     }
     block_minmax(kmn, kmx, red);
 }
