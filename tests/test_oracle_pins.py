@@ -519,12 +519,14 @@ def test_degenerate_shapes():
         assert np.array_equal(r.recon.view(np.uint32), y.view(np.uint32))
 
 
-def test_psnr_definition():
-    # PSNR = 20 log10(range) - 10 log10(MSE) (Sec. 6.1.4)
-    x = np.linspace(-3, 5, 1000).astype(np.float32)
-    y = x + np.float32(0.01)
-    want = 20 * math.log10(8.0) - 10 * math.log10(np.mean((y.astype(np.float64) - x) ** 2))
-    assert abs(O.psnr(x, y) - want) < 1e-9
+def test_psnr_closed_form():
+    # PSNR over the value range (Sec. 6.1.4): values on a 2^-7 grid spanning
+    # 999/128, every one shifted by exactly 2^-6, so MSE = 2^-12 and
+    # PSNR = 20 log10(999/128) + 120 log10(2) = 59.97 dB.
+    x = ((np.arange(1000) - 300) / 128.0).astype(np.float32)
+    y = x + np.float32(2.0 ** -6)
+    assert O.psnr(x, y) == pytest.approx(20 * math.log10(999 / 128) + 120 * math.log10(2), abs=1e-9)
+    assert O.psnr(x, x) == float("inf")
 
 
 def test_huffman_tie_rule_golden(golden_dir):
