@@ -599,6 +599,415 @@ int orc_huff_decode(const uint32_t *words, uint64_t n_words, const uint32_t *cou
 }
 
 /* ------------------------------------------------------------------------ */
+/* Reordering of the codes by interpolation level (Sec. 5.1.4, Eq. reorder)   */
+/* ------------------------------------------------------------------------ */
+
+/* Interpolation level of a point: the largest l <= log2(A) = 4 such that 2^l
+ * divides x, y and z (Eq. reorder). Level 4 holds the anchors, level 0 the
+ * stride-1 targets. */
+int orc_level(uint64_t x, uint64_t y, uint64_t z)
+{
+    int l = 0;
+    while (l < 4 && ((x | y | z) & ((2ull << l) - 1)) == 0)
+        l++;
+    return l;
+}
+
+/* f(k) of Eq. reorder: f(0) = floor((d+1)/2), f(k+1) = floor((f(k)+1)/2);
+ * f(-1) = d. */
+static uint64_t reorder_f(uint64_t d, int k)
+{
+    uint64_t f = d;
+    for (int i = 0; i <= k; i++)
+        f = (f + 1) / 2;
+    return f;
+}
+
+/* Index of point (x, y, z) in the reordered code sequence (Eq. reorder).
+ * Reading: the equation as printed applies the level-0 grid's counts at
+ * every level and is not a bijection for l >= 1. It is applied here on the
+ * level-l grid: coordinates x/2^l, y/2^l, z/2^l, dimension sizes f(l-1)
+ * (f(-1) = d), and the subtractions count the grid points of coarser levels
+ * that precede the point in row-major order. prefix(l) = f_x(l) f_y(l) f_z(l)
+ * is the number of points on coarser levels; the anchor level l = log2(A)
+ * has prefix 0 and no subtraction. At l = 0 this is the printed formula. */
+uint64_t orc_reorder_index(const uint64_t dims[3], uint64_t x, uint64_t y, uint64_t z)
+{
+    const int l = orc_level(x, y, z);
+    const uint64_t xs = x >> l, ys = y >> l, zs = z >> l;
+    const uint64_t dy = reorder_f(dims[1], l - 1), dz = reorder_f(dims[2], l - 1);
+    uint64_t I = xs * dy * dz + ys * dz + zs;
+    if (l == 4)
+        return I;
+    const uint64_t prefix =
+        reorder_f(dims[0], l) * reorder_f(dims[1], l) * reorder_f(dims[2], l);
+    I -= ((xs + 1) / 2) * ((dy + 1) / 2) * ((dz + 1) / 2);
+    if (xs % 2 == 0)
+        I -= ((ys + 1) / 2) * ((dz + 1) / 2);
+    if (xs % 2 == 0 && ys % 2 == 0)
+        I -= (zs + 1) / 2;
+    return prefix + I;
+}
+
+/* seq[I(x,y,z)] = codes[x,y,z]. */
+void orc_reorder(const uint8_t *codes, const uint64_t dims[3], uint8_t *seq)
+{
+    for (uint64_t x = 0; x < dims[0]; x++)
+        for (uint64_t y = 0; y < dims[1]; y++)
+            for (uint64_t z = 0; z < dims[2]; z++)
+                seq[orc_reorder_index(dims, x, y, z)] = codes[gindex(dims, x, y, z)];
+}
+
+void orc_unreorder(const uint8_t *seq, const uint64_t dims[3], uint8_t *codes)
+{
+    for (uint64_t x = 0; x < dims[0]; x++)
+        for (uint64_t y = 0; y < dims[1]; y++)
+            for (uint64_t z = 0; z < dims[2]; z++)
+                codes[gindex(dims, x, y, z)] = seq[orc_reorder_index(dims, x, y, z)];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bitwise-redundancy lossless stages (Sec. 5.2.3)                            */
+/* ------------------------------------------------------------------------ */
+/* The input bytes are cut into chunks of LC_CHUNK bytes (the last may be
+ * shorter); every chunk passes through the pipeline's stages one after the
+ * other, and is stored raw when the result is not smaller than the chunk.
+ * The number in a stage's name is its symbol width k in bytes; a chunk's
+ * trailing bytes that do not fill a whole symbol pass through unchanged.
+ *  - TCMS_k: two's complement to magnitude-sign, (w << 1) ^ (w >> (8k-1))
+ *    with an arithmetic right shift, on each k-byte little-endian word.
+ *  - BIT_1: bit shuffle. The chunk's bytes are taken in groups of 8; output
+ *    plane p (p = 0..7) holds bit p of every input byte, input byte 8j+i of
+ *    the chunk giving bit i of the plane's byte j. Planes follow each other,
+ *    then the bytes left over after the last whole group.
+ *  - RRE_k: a bitmap marks the words that differ from the word before (the
+ *    word before the first is 0); only the marked words are kept.
+ *  - RZE_k: a bitmap marks the nonzero words; only those are kept.
+ * Stage output of RRE_k / RZE_k: the input length (u16), the bitmap
+ * compressed recursively, the kept words, the trailing bytes. Bitmap bit i
+ * is bit (i & 7) of byte i >> 3. Recursive bitmap compression (reading of
+ * "compressing the bitmap recursively"): a bitmap of at most 8 bytes is
+ * stored as it is; a longer one is replaced by the bitmap of its bytes that
+ * differ from the byte before (the byte before the first is 0), itself
+ * compressed the same way, followed by those bytes.
+ * The stage details beyond the paper's sentences (chunk size, symbol order,
+ * bitmap layout, recursion, raw fallback) are this implementation's reading. */
+
+#define LC_CHUNK 16384
+#define LC_MAXBUF (LC_CHUNK + LC_CHUNK / 4 + 64)
+
+enum { ST_TCMS = 0, ST_BIT = 1, ST_RRE = 2, ST_RZE = 3 };
+typedef struct {
+    int op, k;
+} lc_stage;
+
+static const lc_stage TP_STAGES[3] = {{ST_TCMS, 1}, {ST_BIT, 1}, {ST_RRE, 1}};
+static const lc_stage CR_STAGES[3] = {{ST_RRE, 4}, {ST_TCMS, 8}, {ST_RZE, 1}};
+
+static uint64_t get_word(const uint8_t *p, int k)
+{
+    uint64_t v = 0;
+    for (int b = 0; b < k; b++)
+        v |= (uint64_t)p[b] << (8 * b);
+    return v;
+}
+
+static void put_word(uint8_t *p, int k, uint64_t v)
+{
+    for (int b = 0; b < k; b++)
+        p[b] = (uint8_t)(v >> (8 * b));
+}
+
+static void tcms(const uint8_t *in, int n, int k, uint8_t *out)
+{
+    const int bits = 8 * k, m = n / k;
+    const uint64_t mask = bits == 64 ? ~0ull : ((1ull << bits) - 1);
+    memcpy(out, in, (size_t)n);
+    for (int i = 0; i < m; i++) {
+        uint64_t w = get_word(in + (size_t)i * k, k);
+        uint64_t sign = (w >> (bits - 1)) & 1 ? mask : 0; /* arithmetic shift by bits-1 */
+        put_word(out + (size_t)i * k, k, ((w << 1) & mask) ^ sign);
+    }
+}
+
+static void tcms_inv(const uint8_t *in, int n, int k, uint8_t *out)
+{
+    const int bits = 8 * k, m = n / k;
+    const uint64_t mask = bits == 64 ? ~0ull : ((1ull << bits) - 1);
+    memcpy(out, in, (size_t)n);
+    for (int i = 0; i < m; i++) {
+        uint64_t u = get_word(in + (size_t)i * k, k);
+        uint64_t w = (u >> 1) ^ ((u & 1) ? mask : 0);
+        put_word(out + (size_t)i * k, k, w & mask);
+    }
+}
+
+static void bitshuffle(const uint8_t *in, int n, uint8_t *out)
+{
+    const int g = n / 8;
+    for (int p = 0; p < 8; p++)
+        for (int j = 0; j < g; j++) {
+            uint8_t v = 0;
+            for (int i = 0; i < 8; i++)
+                v |= (uint8_t)(((in[8 * j + i] >> p) & 1) << i);
+            out[p * g + j] = v;
+        }
+    memcpy(out + 8 * g, in + 8 * g, (size_t)(n - 8 * g));
+}
+
+static void bitshuffle_inv(const uint8_t *in, int n, uint8_t *out)
+{
+    const int g = n / 8;
+    for (int j = 0; j < 8 * g; j++)
+        out[j] = 0;
+    for (int p = 0; p < 8; p++)
+        for (int j = 0; j < g; j++)
+            for (int i = 0; i < 8; i++)
+                out[8 * j + i] |= (uint8_t)(((in[p * g + j] >> i) & 1) << p);
+    memcpy(out + 8 * g, in + 8 * g, (size_t)(n - 8 * g));
+}
+
+/* Bitmap of nbytes bytes, compressed recursively; returns bytes written. */
+static int bitmap_put(const uint8_t *bm, int nbytes, uint8_t *out)
+{
+    if (nbytes <= 8) {
+        memcpy(out, bm, (size_t)nbytes);
+        return nbytes;
+    }
+    uint8_t sub[LC_MAXBUF / 8 + 8];
+    const int sb = (nbytes + 7) / 8;
+    memset(sub, 0, (size_t)sb);
+    for (int j = 0; j < nbytes; j++) {
+        uint8_t before = j ? bm[j - 1] : 0;
+        if (bm[j] != before)
+            sub[j >> 3] |= (uint8_t)(1u << (j & 7));
+    }
+    int o = bitmap_put(sub, sb, out);
+    for (int j = 0; j < nbytes; j++) {
+        uint8_t before = j ? bm[j - 1] : 0;
+        if (bm[j] != before)
+            out[o++] = bm[j];
+    }
+    return o;
+}
+
+/* Inverse of bitmap_put: rebuilds nbytes bitmap bytes from in[0..avail);
+ * returns the bytes read, or -1 if the input is too short. */
+static int bitmap_get(const uint8_t *in, int avail, int nbytes, uint8_t *bm)
+{
+    if (nbytes <= 8) {
+        if (avail < nbytes)
+            return -1;
+        memcpy(bm, in, (size_t)nbytes);
+        return nbytes;
+    }
+    uint8_t sub[LC_MAXBUF / 8 + 8];
+    const int sb = (nbytes + 7) / 8;
+    int o = bitmap_get(in, avail, sb, sub);
+    if (o < 0)
+        return -1;
+    uint8_t before = 0;
+    for (int j = 0; j < nbytes; j++) {
+        if ((sub[j >> 3] >> (j & 7)) & 1) {
+            if (o >= avail)
+                return -1;
+            before = in[o++];
+        }
+        bm[j] = before;
+    }
+    return o;
+}
+
+/* RRE_k (zero_mode 0) or RZE_k (zero_mode 1) of n bytes; returns the output size. */
+static int reduce(const uint8_t *in, int n, int k, int zero_mode, uint8_t *out)
+{
+    const int m = n / k, tail = n - m * k;
+    uint8_t bm[LC_MAXBUF / 8 + 8];
+    const int nb = (m + 7) / 8;
+    memset(bm, 0, (size_t)nb);
+    uint64_t prev = 0;
+    for (int i = 0; i < m; i++) {
+        uint64_t w = get_word(in + (size_t)i * k, k);
+        int keep = zero_mode ? (w != 0) : (w != prev);
+        if (keep)
+            bm[i >> 3] |= (uint8_t)(1u << (i & 7));
+        prev = w;
+    }
+    out[0] = (uint8_t)(n & 255);
+    out[1] = (uint8_t)(n >> 8);
+    int o = 2 + bitmap_put(bm, nb, out + 2);
+    for (int i = 0; i < m; i++)
+        if ((bm[i >> 3] >> (i & 7)) & 1) {
+            memcpy(out + o, in + (size_t)i * k, (size_t)k);
+            o += k;
+        }
+    memcpy(out + o, in + (size_t)m * k, (size_t)tail);
+    return o + tail;
+}
+
+/* Inverse of reduce; returns the restored length, -1 on a malformed input. */
+static int reduce_inv(const uint8_t *in, int avail, int k, int zero_mode, uint8_t *out,
+                      int out_cap)
+{
+    if (avail < 2)
+        return -1;
+    const int n = in[0] | (in[1] << 8);
+    if (n > out_cap)
+        return -1;
+    const int m = n / k, tail = n - m * k;
+    uint8_t bm[LC_MAXBUF / 8 + 8];
+    const int nb = (m + 7) / 8;
+    int o = bitmap_get(in + 2, avail - 2, nb, bm);
+    if (o < 0)
+        return -1;
+    o += 2;
+    uint64_t prev = 0;
+    for (int i = 0; i < m; i++) {
+        uint64_t w;
+        if ((bm[i >> 3] >> (i & 7)) & 1) {
+            if (o + k > avail)
+                return -1;
+            w = get_word(in + o, k);
+            o += k;
+        } else {
+            w = zero_mode ? 0 : prev;
+        }
+        put_word(out + (size_t)i * k, k, w);
+        prev = w;
+    }
+    if (o + tail != avail)
+        return -1;
+    memcpy(out + (size_t)m * k, in + o, (size_t)tail);
+    return n;
+}
+
+/* One chunk through the stages; returns the encoded size (raw if not smaller). */
+static int lc_chunk_encode(const lc_stage *st, int ns, const uint8_t *in, int n, uint8_t *out)
+{
+    uint8_t a[LC_MAXBUF], b[LC_MAXBUF];
+    memcpy(a, in, (size_t)n);
+    int len = n;
+    for (int i = 0; i < ns; i++) {
+        if (st[i].op == ST_TCMS)
+            tcms(a, len, st[i].k, b);
+        else if (st[i].op == ST_BIT)
+            bitshuffle(a, len, b);
+        else
+            len = reduce(a, len, st[i].k, st[i].op == ST_RZE, b);
+        memcpy(a, b, (size_t)len);
+    }
+    if (len >= n) {
+        memcpy(out, in, (size_t)n);
+        return n;
+    }
+    memcpy(out, a, (size_t)len);
+    return len;
+}
+
+/* Inverse of lc_chunk_encode for a chunk of n raw bytes stored in `size` bytes. */
+static int lc_chunk_decode(const lc_stage *st, int ns, const uint8_t *in, int size, int n,
+                           uint8_t *out)
+{
+    if (size == n) {
+        memcpy(out, in, (size_t)n);
+        return ORC_OK;
+    }
+    if (size > n)
+        return ORC_ERR_CORRUPT;
+    uint8_t a[LC_MAXBUF], b[LC_MAXBUF];
+    memcpy(a, in, (size_t)size);
+    int len = size;
+    for (int i = ns - 1; i >= 0; i--) {
+        if (st[i].op == ST_TCMS)
+            tcms_inv(a, len, st[i].k, b);
+        else if (st[i].op == ST_BIT)
+            bitshuffle_inv(a, len, b);
+        else {
+            len = reduce_inv(a, len, st[i].k, st[i].op == ST_RZE, b, LC_MAXBUF);
+            if (len < 0)
+                return ORC_ERR_CORRUPT;
+        }
+        memcpy(a, b, (size_t)len);
+    }
+    if (len != n)
+        return ORC_ERR_CORRUPT;
+    memcpy(out, a, (size_t)n);
+    return ORC_OK;
+}
+
+static const lc_stage *pipeline_stages(int pipe)
+{
+    return pipe == ORC_PIPE_TP ? TP_STAGES : CR_STAGES;
+}
+
+uint64_t orc_lc_chunks(uint64_t n) { return cdiv(n, LC_CHUNK); }
+
+/* Chunked pipeline over n bytes: sizes[k] = stored bytes of chunk k; data
+ * must hold n bytes (a chunk never stores more than its raw size). */
+int orc_lc_encode(int pipe, const uint8_t *in, uint64_t n, uint32_t *sizes, uint8_t *data,
+                  uint64_t *data_bytes)
+{
+    if (pipe != ORC_PIPE_TP && pipe != ORC_PIPE_CR)
+        return ORC_ERR_ARG;
+    const lc_stage *st = pipeline_stages(pipe);
+    uint64_t o = 0;
+    for (uint64_t c = 0; c < orc_lc_chunks(n); c++) {
+        const uint64_t lo = c * LC_CHUNK;
+        const int len = (int)(lo + LC_CHUNK <= n ? LC_CHUNK : n - lo);
+        const int sz = lc_chunk_encode(st, 3, in + lo, len, data + o);
+        sizes[c] = (uint32_t)sz;
+        o += (uint64_t)sz;
+    }
+    *data_bytes = o;
+    return ORC_OK;
+}
+
+int orc_lc_decode(int pipe, const uint32_t *sizes, const uint8_t *data, uint64_t data_bytes,
+                  uint8_t *out, uint64_t n)
+{
+    if (pipe != ORC_PIPE_TP && pipe != ORC_PIPE_CR)
+        return ORC_ERR_ARG;
+    const lc_stage *st = pipeline_stages(pipe);
+    uint64_t o = 0;
+    for (uint64_t c = 0; c < orc_lc_chunks(n); c++) {
+        const uint64_t lo = c * LC_CHUNK;
+        const int len = (int)(lo + LC_CHUNK <= n ? LC_CHUNK : n - lo);
+        if (sizes[c] > (uint32_t)len || o + sizes[c] > data_bytes)
+            return ORC_ERR_CORRUPT;
+        int rc = lc_chunk_decode(st, 3, data + o, (int)sizes[c], len, out + lo);
+        if (rc)
+            return rc;
+        o += sizes[c];
+    }
+    return o == data_bytes ? ORC_OK : ORC_ERR_CORRUPT;
+}
+
+/* One stage on one buffer (tests): op 0 TCMS, 1 BIT, 2 RRE, 3 RZE; inverse
+ * when inv != 0. Returns the output length or -1. */
+int orc_lc_stage(int op, int k, int inv, const uint8_t *in, int n, uint8_t *out)
+{
+    if (n < 0 || n > LC_MAXBUF - 64)
+        return -1;
+    if (op == ST_TCMS) {
+        if (k != 1 && k != 2 && k != 4 && k != 8)
+            return -1;
+        (inv ? tcms_inv : tcms)(in, n, k, out);
+        return n;
+    }
+    if (op == ST_BIT) {
+        (inv ? bitshuffle_inv : bitshuffle)(in, n, out);
+        return n;
+    }
+    if (op == ST_RRE || op == ST_RZE) {
+        if (k != 1 && k != 2 && k != 4 && k != 8)
+            return -1;
+        return inv ? reduce_inv(in, n, k, op == ST_RZE, out, LC_MAXBUF)
+                   : reduce(in, n, k, op == ST_RZE, out);
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Stream                                                                     */
 /* ------------------------------------------------------------------------ */
 
@@ -623,15 +1032,31 @@ typedef struct {
     uint64_t n_out, payload_words, total, n_chunks, n_anchors;
     uint64_t off_anchors, off_oidx, off_oval, off_payload;
     int idx_bytes;
+    int pipe;                 /* lossless pipeline (ORC_PIPE_*) */
+    uint64_t n_lc, lc_bytes;  /* TP / CR: chunks and stored bytes of the last stages */
+    uint64_t off_lcsizes;     /* CR: chunk-size table of the last stages */
 } layout;
 
+/* Section offsets. HF: Huffman word counts at 384, payload last. TP: the
+ * last stages' chunk sizes at 384 (no Huffman sections), their data last.
+ * CR: Huffman word counts at 384, then after the outliers the last stages'
+ * chunk sizes and their data (the Huffman payload after those stages). */
 static void compute_offsets(layout *L)
 {
-    L->off_anchors = align16(OFF_CHUNKS + 4 * L->n_chunks);
+    const uint64_t table = L->pipe == ORC_PIPE_TP ? L->n_lc : L->n_chunks;
+    L->off_anchors = align16(OFF_CHUNKS + 4 * table);
     L->off_oidx = align16(L->off_anchors + 4 * L->n_anchors);
     L->off_oval = align16(L->off_oidx + (uint64_t)L->idx_bytes * L->n_out);
-    L->off_payload = align16(L->off_oval + 4 * L->n_out);
-    L->total = L->off_payload + 4 * L->payload_words;
+    const uint64_t end_oval = L->off_oval + 4 * L->n_out;
+    if (L->pipe == ORC_PIPE_HF) {
+        L->off_payload = align16(end_oval);
+        L->total = L->off_payload + 4 * L->payload_words;
+        return;
+    }
+    L->off_lcsizes = L->pipe == ORC_PIPE_TP ? OFF_CHUNKS : align16(end_oval);
+    L->off_payload = L->pipe == ORC_PIPE_TP ? align16(end_oval)
+                                            : align16(L->off_lcsizes + 4 * L->n_lc);
+    L->total = L->off_payload + L->lc_bytes;
 }
 
 static void write_header(uint8_t *o, const layout *L)
@@ -659,6 +1084,9 @@ static void write_header(uint8_t *o, const layout *L)
     put_u64(o + 88, L->total);
     put_u64(o + 96, L->n_chunks);
     put_u64(o + 104, L->n_anchors);
+    o[54] = (uint8_t)L->pipe;
+    put_u64(o + 112, L->lc_bytes);
+    put_u64(o + 120, L->n_lc);
 }
 
 /* Exact minimum and maximum; -0.0 counts as smaller than +0.0. */
@@ -693,8 +1121,13 @@ int orc_compress(const float *x, const uint64_t dims[3], int mode, double eb,
         prm.tune = 1;
         prm.chunk = 1024;
         default_cfg(prm.cfg);
+        prm.pipeline = ORC_PIPE_HF;
+        prm.reorder = 0;
     }
     if (prm.chunk < 256 || prm.chunk > 65536 || (prm.chunk & (prm.chunk - 1)))
+        return ORC_ERR_ARG;
+    if (prm.pipeline < ORC_PIPE_HF || prm.pipeline > ORC_PIPE_CR ||
+        (prm.reorder != 0 && prm.reorder != 1))
         return ORC_ERR_ARG;
     for (int l = 0; l < 4; l++)
         if (prm.cfg[l][0] > 1 || prm.cfg[l][1] > 1 || prm.cfg[l][2] > 5)
@@ -720,11 +1153,13 @@ int orc_compress(const float *x, const uint64_t dims[3], int mode, double eb,
     L.vmin = vmin;
     L.vmax = vmax;
     L.chunk = prm.chunk;
+    L.pipe = prm.pipeline;
 
     if (mode == ORC_REL && (double)vmax - (double)vmin == 0.0) {
         /* Constant field: the header and the single value. */
         L.flags = 1;
         L.eps = 0.0f;
+        L.pipe = ORC_PIPE_HF;
         L.total = HDR_BYTES + 4;
         uint8_t *o = calloc(L.total, 1);
         if (!o)
@@ -813,26 +1248,72 @@ int orc_compress(const float *x, const uint64_t dims[3], int mode, double eb,
 
     uint8_t len[256];
     uint32_t code[256];
-    orc_codebook(hist, len, code);
+    memset(len, 0, sizeof(len));
+    if (L.pipe != ORC_PIPE_TP)
+        orc_codebook(hist, len, code);
 
-    uint32_t *words = malloc(sizeof(uint32_t) * (N + L.n_chunks));
-    uint32_t *counts = malloc(sizeof(uint32_t) * (L.n_chunks ? L.n_chunks : 1));
-    if (!words || !counts) {
+    /* The lossless stage reads the codes in row-major order, or reordered by
+     * level (Sec. 5.1.4, Eq. reorder) when asked. */
+    uint8_t *seq = codes;
+    if (prm.reorder) {
+        seq = malloc(N);
+        if (!seq) {
+            free(codes);
+            free(anchors);
+            return ORC_ERR_NOMEM;
+        }
+        orc_reorder(codes, dims, seq);
+        L.flags |= ORC_FLAG_REORDER;
+    }
+    /* Huffman payload (HF and CR; Sec. 5.2.2-5.2.3) */
+    uint32_t *words = NULL, *counts = NULL;
+    uint64_t nw = 0;
+    if (L.pipe != ORC_PIPE_TP) {
+        L.n_chunks = cdiv(N, prm.chunk);
+        words = malloc(sizeof(uint32_t) * (N + L.n_chunks));
+        counts = malloc(sizeof(uint32_t) * (L.n_chunks ? L.n_chunks : 1));
+        if (words && counts)
+            orc_huff_encode(seq, N, prm.chunk, len, code, words, &nw, counts);
+    } else {
+        L.n_chunks = 0;
+        L.chunk = 0;
+    }
+    /* the bitwise-redundancy stages (Sec. 5.2.3): TP on the codes, CR on the
+     * Huffman payload's bytes (words little-endian) */
+    uint32_t *lc_sizes = NULL;
+    uint8_t *lc_data = NULL;
+    int fail_mem = (L.pipe != ORC_PIPE_TP && (!words || !counts));
+    if (!fail_mem && L.pipe != ORC_PIPE_HF) {
+        const uint8_t *lc_in = L.pipe == ORC_PIPE_TP ? seq : (const uint8_t *)words;
+        const uint64_t n_in = L.pipe == ORC_PIPE_TP ? N : 4 * nw;
+        L.n_lc = orc_lc_chunks(n_in);
+        lc_sizes = malloc(sizeof(uint32_t) * (L.n_lc ? L.n_lc : 1));
+        lc_data = malloc(n_in ? n_in : 1);
+        if (lc_sizes && lc_data)
+            orc_lc_encode(L.pipe, lc_in, n_in, lc_sizes, lc_data, &L.lc_bytes);
+        else
+            fail_mem = 1;
+    }
+    if (seq != codes)
+        free(seq);
+    if (fail_mem) {
         free(words);
         free(counts);
+        free(lc_sizes);
+        free(lc_data);
         free(codes);
         free(anchors);
         return ORC_ERR_NOMEM;
     }
-    uint64_t nw = 0;
-    orc_huff_encode(codes, N, prm.chunk, len, code, words, &nw, counts);
-    L.payload_words = nw;
+    L.payload_words = L.pipe == ORC_PIPE_TP ? 0 : nw;
     compute_offsets(&L);
 
     uint8_t *o = calloc(L.total, 1);
     if (!o) {
         free(words);
         free(counts);
+        free(lc_sizes);
+        free(lc_data);
         free(codes);
         free(anchors);
         return ORC_ERR_NOMEM;
@@ -854,8 +1335,16 @@ int orc_compress(const float *x, const uint64_t dims[3], int mode, double eb,
             put_f32(o + L.off_oval + 4 * j, x[i]);
             j++;
         }
-    for (uint64_t k = 0; k < nw; k++)
-        put_u32(o + L.off_payload + 4 * k, words[k]);
+    if (L.pipe == ORC_PIPE_HF) {
+        for (uint64_t k = 0; k < nw; k++)
+            put_u32(o + L.off_payload + 4 * k, words[k]);
+    } else {
+        for (uint64_t k = 0; k < L.n_lc; k++)
+            put_u32(o + L.off_lcsizes + 4 * k, lc_sizes[k]);
+        memcpy(o + L.off_payload, lc_data, L.lc_bytes);
+    }
+    free(lc_sizes);
+    free(lc_data);
 
     if (dbg) {
         memcpy(dbg->hist, hist, sizeof(hist));
@@ -897,9 +1386,12 @@ static int parse_header(const uint8_t *in, uint64_t in_size, layout *L)
     L->eps = get_f32(in + 40);
     L->vmin = get_f32(in + 44);
     L->vmax = get_f32(in + 48);
-    if (L->mode > 1 || (L->flags & ~3))
+    L->pipe = in[54];
+    if (L->mode > 1 || (L->flags & ~7) || L->pipe > ORC_PIPE_CR)
         return ORC_ERR_CORRUPT;
     if (L->flags & 1) {
+        if (L->pipe != ORC_PIPE_HF || (L->flags & ORC_FLAG_REORDER))
+            return ORC_ERR_CORRUPT;
         L->total = HDR_BYTES + 4;
         if (in_size < L->total || get_u64(in + 88) != L->total)
             return ORC_ERR_CORRUPT;
@@ -914,21 +1406,37 @@ static int parse_header(const uint8_t *in, uint64_t in_size, layout *L)
             return ORC_ERR_CORRUPT;
     }
     L->chunk = get_u32(in + 68);
-    if (L->chunk < 256 || L->chunk > 65536 || (L->chunk & (L->chunk - 1)))
-        return ORC_ERR_CORRUPT;
     L->n_out = get_u64(in + 72);
     L->payload_words = get_u64(in + 80);
     L->n_chunks = get_u64(in + 96);
     L->n_anchors = get_u64(in + 104);
+    L->lc_bytes = get_u64(in + 112);
+    L->n_lc = get_u64(in + 120);
+    if (L->pipe == ORC_PIPE_TP) {
+        if (L->chunk != 0 || L->n_chunks != 0 || L->payload_words != 0)
+            return ORC_ERR_CORRUPT;
+        if (L->n_lc != orc_lc_chunks(L->N) || L->lc_bytes > L->N)
+            return ORC_ERR_CORRUPT;
+    } else {
+        if (L->chunk < 256 || L->chunk > 65536 || (L->chunk & (L->chunk - 1)))
+            return ORC_ERR_CORRUPT;
+        if (L->n_chunks != cdiv(L->N, L->chunk))
+            return ORC_ERR_CORRUPT;
+        if (L->payload_words > L->N + L->n_chunks)
+            return ORC_ERR_CORRUPT;
+        if (L->pipe == ORC_PIPE_HF && (L->n_lc != 0 || L->lc_bytes != 0))
+            return ORC_ERR_CORRUPT;
+        if (L->pipe == ORC_PIPE_CR && (L->n_lc != orc_lc_chunks(4 * L->payload_words) ||
+                                       L->lc_bytes > 4 * L->payload_words))
+            return ORC_ERR_CORRUPT;
+    }
     L->idx_bytes = L->N < (1ull << 32) ? 4 : 8;
     if (((L->flags & 2) != 0) != (L->idx_bytes == 8))
-        return ORC_ERR_CORRUPT;
-    if (L->n_chunks != cdiv(L->N, L->chunk))
         return ORC_ERR_CORRUPT;
     if (L->n_anchors != cdiv(L->dims[0], ANCHOR) * cdiv(L->dims[1], ANCHOR) *
                             cdiv(L->dims[2], ANCHOR))
         return ORC_ERR_CORRUPT;
-    if (L->n_out > L->N || L->payload_words > L->N + L->n_chunks)
+    if (L->n_out > L->N)
         return ORC_ERR_CORRUPT;
     compute_offsets(L);
     if (get_u64(in + 88) != L->total || L->total > in_size)
@@ -986,39 +1494,67 @@ int orc_decompress(const uint8_t *in, uint64_t in_size, float *out,
         return ORC_OK;
     }
     const uint8_t *len = in + OFF_LEN;
-    /* Kraft sum must not exceed one; a single symbol has length one. */
-    double kraft = 0.0;
-    int nsym = 0;
-    for (int i = 0; i < 256; i++)
-        if (len[i]) {
-            if (len[i] > MAX_CODE_LEN)
-                return ORC_ERR_CORRUPT;
-            kraft += ldexp(1.0, -len[i]);
-            nsym++;
-        }
-    if (nsym == 0 || (nsym == 1 && kraft != 0.5) || (nsym > 1 && kraft != 1.0))
-        return ORC_ERR_CORRUPT;
-    uint32_t *counts = malloc(sizeof(uint32_t) * L.n_chunks);
-    uint32_t *words = malloc(sizeof(uint32_t) * (L.payload_words ? L.payload_words : 1));
     uint8_t *codes = malloc(N);
-    if (!counts || !words || !codes) {
-        free(counts);
-        free(words);
+    uint8_t *seq = (L.flags & ORC_FLAG_REORDER) ? malloc(N) : codes;
+    if (!codes || !seq) {
         free(codes);
+        if (seq != codes)
+            free(seq);
         return ORC_ERR_NOMEM;
     }
-    uint64_t sum = 0;
-    for (uint64_t k = 0; k < L.n_chunks; k++) {
-        counts[k] = get_u32(in + OFF_CHUNKS + 4 * k);
-        sum += counts[k];
+    rc = ORC_OK;
+    /* the last stages (TP, CR): their chunk sizes, then their data */
+    uint8_t *lc_out = NULL;
+    if (L.pipe != ORC_PIPE_HF) {
+        const uint64_t n_raw = L.pipe == ORC_PIPE_TP ? N : 4 * L.payload_words;
+        uint32_t *sizes = malloc(sizeof(uint32_t) * (L.n_lc ? L.n_lc : 1));
+        lc_out = L.pipe == ORC_PIPE_TP ? seq : malloc(n_raw ? n_raw : 1);
+        if (!sizes || !lc_out)
+            rc = ORC_ERR_NOMEM;
+        for (uint64_t k = 0; !rc && k < L.n_lc; k++)
+            sizes[k] = get_u32(in + L.off_lcsizes + 4 * k);
+        if (!rc)
+            rc = orc_lc_decode(L.pipe, sizes, in + L.off_payload, L.lc_bytes, lc_out, n_raw);
+        free(sizes);
     }
-    for (uint64_t k = 0; k < L.payload_words; k++)
-        words[k] = get_u32(in + L.off_payload + 4 * k);
-    rc = sum == L.payload_words ? ORC_OK : ORC_ERR_CORRUPT;
-    if (!rc)
-        rc = orc_huff_decode(words, L.payload_words, counts, N, L.chunk, len, codes);
-    free(words);
-    free(counts);
+    if (!rc && L.pipe != ORC_PIPE_TP) {
+        /* Kraft sum must not exceed one; a single symbol has length one. */
+        double kraft = 0.0;
+        int nsym = 0;
+        for (int i = 0; i < 256; i++)
+            if (len[i]) {
+                if (len[i] > MAX_CODE_LEN)
+                    rc = ORC_ERR_CORRUPT;
+                kraft += ldexp(1.0, -len[i]);
+                nsym++;
+            }
+        if (nsym == 0 || (nsym == 1 && kraft != 0.5) || (nsym > 1 && kraft != 1.0))
+            rc = ORC_ERR_CORRUPT;
+        uint32_t *counts = malloc(sizeof(uint32_t) * (L.n_chunks ? L.n_chunks : 1));
+        uint32_t *words = malloc(sizeof(uint32_t) * (L.payload_words ? L.payload_words : 1));
+        if (!rc && (!counts || !words))
+            rc = ORC_ERR_NOMEM;
+        uint64_t sum = 0;
+        for (uint64_t k = 0; !rc && k < L.n_chunks; k++) {
+            counts[k] = get_u32(in + OFF_CHUNKS + 4 * k);
+            sum += counts[k];
+        }
+        for (uint64_t k = 0; !rc && k < L.payload_words; k++)
+            words[k] = L.pipe == ORC_PIPE_HF ? get_u32(in + L.off_payload + 4 * k)
+                                             : get_u32(lc_out + 4 * k);
+        if (!rc && sum != L.payload_words)
+            rc = ORC_ERR_CORRUPT;
+        if (!rc)
+            rc = orc_huff_decode(words, L.payload_words, counts, N, L.chunk, len, seq);
+        free(words);
+        free(counts);
+    }
+    if (lc_out && lc_out != seq)
+        free(lc_out);
+    if (!rc && seq != codes)
+        orc_unreorder(seq, L.dims, codes);
+    if (seq != codes)
+        free(seq);
     if (!rc) {
         uint64_t zeros = 0, prev = 0;
         for (uint64_t i = 0; i < N; i++)

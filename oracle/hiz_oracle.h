@@ -36,6 +36,12 @@ enum {
 enum { ORC_ABS = 0, ORC_REL = 1 };
 enum { ORC_LIN = 0, ORC_CUB = 1 };
 enum { ORC_MD = 0, ORC_SEQ = 1 };
+/* Lossless pipelines (Sec. 5.2.3): Huffman only; TCMS1-BIT1-RRE1 on the codes
+ * (no Huffman, the throughput mode); Huffman then RRE4-TCMS8-RZE1 on its
+ * payload (the ratio mode). */
+enum { ORC_PIPE_HF = 0, ORC_PIPE_TP = 1, ORC_PIPE_CR = 2 };
+/* stream flag: codes reordered by level (Sec. 5.1.4) before the lossless stage */
+enum { ORC_FLAG_REORDER = 4 };
 
 /* Per-level interpolation configuration, levels ordered by stride 8, 4, 2, 1.
  * cfg[l][0] = spline (ORC_LIN/ORC_CUB), cfg[l][1] = scheme (ORC_MD/ORC_SEQ),
@@ -45,6 +51,8 @@ typedef struct {
     int tune;              /* 1: choose cfg with the sampled-block tuner */
     uint8_t cfg[4][3];     /* used when tune == 0 */
     uint32_t chunk;        /* Huffman chunk length in symbols (power of 2, 256..65536) */
+    int pipeline;          /* ORC_PIPE_* */
+    int reorder;           /* 1: reorder the codes by level (Eq. reorder) first */
 } orc_params;
 
 /* Optional debug outputs of compress (any pointer may be NULL). */
@@ -90,6 +98,25 @@ int orc_huff_encode(const uint8_t *codes, uint64_t n, uint32_t chunk,
                     uint32_t *words, uint64_t *n_words, uint32_t *counts);
 int orc_huff_decode(const uint32_t *words, uint64_t n_words, const uint32_t *counts,
                     uint64_t n, uint32_t chunk, const uint8_t len[256], uint8_t *codes);
+
+/* Level of a point and its index in the reordered code sequence
+ * (Sec. 5.1.4, Eq. reorder); reorder / unreorder the whole code array. */
+int orc_level(uint64_t x, uint64_t y, uint64_t z);
+uint64_t orc_reorder_index(const uint64_t dims[3], uint64_t x, uint64_t y, uint64_t z);
+void orc_reorder(const uint8_t *codes, const uint64_t dims[3], uint8_t *seq);
+void orc_unreorder(const uint8_t *seq, const uint64_t dims[3], uint8_t *codes);
+
+/* Bitwise-redundancy stages (Sec. 5.2.3), chunked: n bytes -> per-chunk
+ * stored sizes and concatenated chunk data (data must hold n bytes). */
+uint64_t orc_lc_chunks(uint64_t n);
+int orc_lc_encode(int pipe, const uint8_t *in, uint64_t n, uint32_t *sizes, uint8_t *data,
+                  uint64_t *data_bytes);
+int orc_lc_decode(int pipe, const uint32_t *sizes, const uint8_t *data, uint64_t data_bytes,
+                  uint8_t *out, uint64_t n);
+/* One stage on one buffer: op 0 TCMS, 1 BIT, 2 RRE, 3 RZE, symbol width k;
+ * the inverse when inv != 0. n is at most 20480; `out` must hold 20544
+ * bytes. Returns the output length, -1 on bad input. */
+int orc_lc_stage(int op, int k, int inv, const uint8_t *in, int n, uint8_t *out);
 
 /* Compress / decompress (Sec. 3.1). The stream is allocated with malloc and
  * released with orc_free. */

@@ -19,6 +19,11 @@ OK, ERR_ARG, ERR_NONFINITE, ERR_BUFSZ, ERR_CORRUPT, ERR_NOMEM = 0, 1, 2, 3, 4, 5
 ABS, REL = 0, 1
 LIN, CUB = 0, 1
 MD, SEQ = 0, 1
+PIPE_HF, PIPE_TP, PIPE_CR = 0, 1, 2
+FLAG_REORDER = 4
+LC_TCMS, LC_BIT, LC_RRE, LC_RZE = 0, 1, 2, 3
+LC_CHUNK = 16384
+LC_STAGE_OUT = 16384 + 16384 // 4 + 64  # output capacity orc_lc_stage assumes
 PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
 
 
@@ -34,7 +39,8 @@ def build(force: bool = False) -> str:
 
 
 class Params(C.Structure):
-    _fields_ = [("tune", C.c_int), ("cfg", (C.c_uint8 * 3) * 4), ("chunk", C.c_uint32)]
+    _fields_ = [("tune", C.c_int), ("cfg", (C.c_uint8 * 3) * 4), ("chunk", C.c_uint32),
+                ("pipeline", C.c_int), ("reorder", C.c_int)]
 
 
 class Debug(C.Structure):
@@ -72,6 +78,19 @@ def lib():
                                      C.c_void_p]
         L.orc_stream_dims.argtypes = [C.c_void_p, C.c_uint64, u64p]
         L.orc_free.argtypes = [C.c_void_p]
+        L.orc_level.argtypes = [C.c_uint64] * 3
+        L.orc_reorder_index.argtypes = [u64p, C.c_uint64, C.c_uint64, C.c_uint64]
+        L.orc_reorder_index.restype = C.c_uint64
+        L.orc_reorder.argtypes = [C.c_void_p, u64p, C.c_void_p]
+        L.orc_reorder.restype = None
+        L.orc_unreorder.argtypes = [C.c_void_p, u64p, C.c_void_p]
+        L.orc_unreorder.restype = None
+        L.orc_lc_chunks.argtypes = [C.c_uint64]
+        L.orc_lc_chunks.restype = C.c_uint64
+        L.orc_lc_encode.argtypes = [C.c_int, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, u64p]
+        L.orc_lc_decode.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
+                                    C.c_uint64]
+        L.orc_lc_stage.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p]
         _lib = L
     return _lib
 
@@ -191,11 +210,11 @@ class Result:
 
 
 def compress(x: np.ndarray, mode, eb, tune=True, cfg=DEFAULT_CFG, chunk=1024,
-             debug=True) -> Result:
+             debug=True, pipeline=PIPE_HF, reorder=False) -> Result:
     x = np.ascontiguousarray(x, dtype=np.float32)
     if x.ndim != 3:
         raise ValueError("oracle.compress needs a 3-D array")
-    p = Params(int(bool(tune)), cfg_array(cfg), int(chunk))
+    p = Params(int(bool(tune)), cfg_array(cfg), int(chunk), int(pipeline), int(bool(reorder)))
     out = C.c_void_p()
     size = C.c_uint64()
     dbg = Debug()
@@ -252,6 +271,65 @@ def decompress_status(stream: np.ndarray) -> int:
     n = int(d[0]) * int(d[1]) * int(d[2])
     out = np.zeros(n, dtype=np.float32)
     return lib().orc_decompress(s.ctypes.data, s.size, out.ctypes.data, n, d, None)
+
+
+def level(x, y, z) -> int:
+    return lib().orc_level(int(x), int(y), int(z))
+
+
+def reorder_index(shape, x, y, z) -> int:
+    return int(lib().orc_reorder_index(_dims(shape), int(x), int(y), int(z)))
+
+
+def reorder(codes: np.ndarray) -> np.ndarray:
+    c = np.ascontiguousarray(codes, dtype=np.uint8)
+    out = np.zeros(c.size, dtype=np.uint8)
+    lib().orc_reorder(c.ctypes.data, _dims(c.shape), out.ctypes.data)
+    return out
+
+
+def unreorder(seq: np.ndarray, shape) -> np.ndarray:
+    s_ = np.ascontiguousarray(seq, dtype=np.uint8)
+    out = np.zeros(shape, dtype=np.uint8)
+    lib().orc_unreorder(s_.ctypes.data, _dims(shape), out.ctypes.data)
+    return out
+
+
+def lc_encode(pipeline, data: np.ndarray):
+    """Chunked bitwise-redundancy stages: (sizes u32[n_chunks], stored bytes)."""
+    d = np.ascontiguousarray(data, dtype=np.uint8)
+    n = d.size
+    nc = int(lib().orc_lc_chunks(n))
+    sizes = np.zeros(max(nc, 1), dtype=np.uint32)
+    out = np.zeros(max(n, 1), dtype=np.uint8)
+    nb = C.c_uint64()
+    rc = lib().orc_lc_encode(int(pipeline), d.ctypes.data, n, sizes.ctypes.data, out.ctypes.data,
+                             C.byref(nb))
+    if rc:
+        raise OracleError(rc, "lc_encode")
+    return sizes[:nc].copy(), out[:nb.value].copy()
+
+
+def lc_decode(pipeline, sizes, stored, n) -> np.ndarray:
+    sz = np.ascontiguousarray(sizes, dtype=np.uint32)
+    st = np.ascontiguousarray(stored, dtype=np.uint8)
+    out = np.zeros(max(int(n), 1), dtype=np.uint8)
+    rc = lib().orc_lc_decode(int(pipeline), sz.ctypes.data, st.ctypes.data, st.size,
+                             out.ctypes.data, int(n))
+    if rc:
+        raise OracleError(rc, "lc_decode")
+    return out[:int(n)].copy()
+
+
+def lc_stage(op, k, data, inverse=False) -> np.ndarray:
+    """One bitwise-redundancy stage on one buffer (at most 20 KB)."""
+    d = np.ascontiguousarray(data, dtype=np.uint8)
+    out = np.zeros(LC_STAGE_OUT, dtype=np.uint8)  # the C routine may write this much
+    n = lib().orc_lc_stage(int(op), int(k), int(bool(inverse)), d.ctypes.data, d.size,
+                           out.ctypes.data)
+    if n < 0:
+        raise OracleError(n, "lc_stage")
+    return out[:n].copy()
 
 
 def psnr(x: np.ndarray, y: np.ndarray) -> float:
