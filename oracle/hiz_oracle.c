@@ -243,6 +243,46 @@ static uint64_t gindex(const uint64_t dims[3], uint64_t x, uint64_t y, uint64_t 
     return (x * dims[1] + y) * dims[2] + z;
 }
 
+#ifdef ORC_FACE_CHECK
+/* Debug check of the shared faces (built only with -DORC_FACE_CHECK): a
+ * block computes the points of its +1 faces itself, and those values must
+ * agree bit for bit with the values every other block containing the point
+ * computed (its owner's included). Each computed point is noted once per
+ * block; a second note with other bits counts as a mismatch. */
+static float *fc_val;
+static uint8_t *fc_set;
+static uint64_t fc_mismatch;
+
+uint64_t orc_face_mismatches(void) { return fc_mismatch; }
+
+static int fc_begin(uint64_t N)
+{
+    fc_mismatch = 0;
+    free(fc_val);
+    free(fc_set);
+    fc_val = malloc(sizeof(float) * (N ? N : 1));
+    fc_set = calloc(N ? N : 1, 1);
+    return fc_val && fc_set;
+}
+
+static void fc_note_block(const float *buf, const block *k, const uint64_t dims[3])
+{
+    for (int i = 0; i < k->n[0]; i++)
+        for (int j = 0; j < k->n[1]; j++)
+            for (int m = 0; m < k->n[2]; m++) {
+                const uint64_t g = gindex(dims, k->o[0] + i, k->o[1] + j, k->o[2] + m);
+                const float v = buf[(i * k->n[1] + j) * k->n[2] + m];
+                if (fc_set[g]) {
+                    if (memcmp(&fc_val[g], &v, sizeof(float)) != 0)
+                        fc_mismatch++;
+                } else {
+                    fc_set[g] = 1;
+                    fc_val[g] = v;
+                }
+            }
+}
+#endif
+
 /* Walk the levels of one block (strides 8, 4, 2, 1), sub-step by sub-step.
  * Compression (codes_in == NULL) predicts from reconstructed values, quantizes
  * and replaces each value by its reconstruction before any later target reads
@@ -1219,6 +1259,14 @@ int orc_compress(const float *x, const uint64_t dims[3], int mode, double eb,
     }
 
     /* Predict and quantize block by block; blocks are independent. */
+#ifdef ORC_FACE_CHECK
+    if (!fc_begin(N)) {
+        free(codes);
+        free(anchors);
+        free(buf);
+        return ORC_ERR_NOMEM;
+    }
+#endif
     for (uint64_t a = 0; a < nb[0]; a++)
         for (uint64_t b = 0; b < nb[1]; b++)
             for (uint64_t c = 0; c < nb[2]; c++) {
@@ -1232,6 +1280,9 @@ int orc_compress(const float *x, const uint64_t dims[3], int mode, double eb,
                 anchors[(a * nb[1] + b) * nb[2] + c] = buf[0];
                 codes[g0] = 128; /* anchors keep the zero-error code */
                 run_levels(buf, &k, L.cfg, eps, two_eb, inv, NULL, codes, dims);
+#ifdef ORC_FACE_CHECK
+                fc_note_block(buf, &k, dims);
+#endif
                 if (dbg && dbg->recon)
                     for (int i = 0; i < k.own[0]; i++)
                         for (int j = 0; j < k.own[1]; j++)
@@ -1585,6 +1636,13 @@ int orc_decompress(const uint8_t *in, uint64_t in_size, float *out,
         free(codes);
         return ORC_ERR_NOMEM;
     }
+#ifdef ORC_FACE_CHECK
+    if (!fc_begin(N)) {
+        free(buf);
+        free(codes);
+        return ORC_ERR_NOMEM;
+    }
+#endif
     for (uint64_t a = 0; a < nb[0] && !rc; a++)
         for (uint64_t b = 0; b < nb[1] && !rc; b++)
             for (uint64_t c = 0; c < nb[2] && !rc; c++) {
@@ -1608,6 +1666,9 @@ int orc_decompress(const uint8_t *in, uint64_t in_size, float *out,
                 if (rc)
                     break;
                 run_levels(buf, &k, L.cfg, L.eps, two_eb, 0.0f, codes, NULL, L.dims);
+#ifdef ORC_FACE_CHECK
+                fc_note_block(buf, &k, L.dims);
+#endif
                 for (int i = 0; i < k.own[0]; i++)
                     for (int j = 0; j < k.own[1]; j++)
                         for (int m = 0; m < k.own[2]; m++)

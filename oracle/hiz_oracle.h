@@ -130,6 +130,12 @@ int orc_stream_dims(const uint8_t *in, uint64_t in_size, uint64_t dims[3]);
 
 void orc_free(void *p);
 
+#ifdef ORC_FACE_CHECK
+/* Debug builds only: shared-face points whose values differed between the
+ * blocks that computed them, over the last compress or decompress call. */
+uint64_t orc_face_mismatches(void);
+#endif
+
 #ifdef __cplusplus
 }
 #endif
