@@ -70,17 +70,22 @@ float orc_eps(int mode, double eb, float vmin, float vmax)
 /* Spline stencils (Sec. 5.1.2)                                               */
 /* ------------------------------------------------------------------------ */
 
-/* Lagrange interpolation at the midpoint from the samples at -3s, -s, +s, +3s.
+/* Interpolation at the midpoint from the samples at -3s, -s, +s, +3s.
  * Cubic needs all four; at block edges the paper falls back to lower orders
  * (quadratic/linear); the reading ranks them cubic > quadratic > linear >
- * linear extrapolation > copy. Weights: (-1,9,9,-1)/16, (3,6,-1)/8,
- * (-1,6,3)/8, (1,1)/2, (-1,3)/2. */
+ * linear extrapolation > copy. Lagrange weights: (-1,9,9,-1)/16, (3,6,-1)/8,
+ * (-1,6,3)/8, (1,1)/2, (-1,3)/2. The paper's "multiple interpolation
+ * splines" (Sec. 5.1.3) add the natural cubic spline through the four
+ * samples (zero second derivative at the outer two), whose value at the
+ * midpoint has weights (-3,23,23,-3)/40; it falls back like the cubic. */
 float orc_stencil(int spline, float a, float b, float c, float d,
                   int pa, int pc, int pd, int *rank)
 {
-    if (spline == ORC_CUB) {
+    if (spline == ORC_CUB || spline == ORC_NAT) {
         if (pa && pc && pd) {
             *rank = 4;
+            if (spline == ORC_NAT)
+                return ((b + c) * 23.0f - (a + d) * 3.0f) / 40.0f;
             return ((b + c) * 9.0f - (a + d)) * 0.0625f;
         }
         if (!pa && pc && pd) {
@@ -338,27 +343,35 @@ static void default_cfg(uint8_t cfg[4][3])
     }
 }
 
-/* Uniformly spaced full 17^3 blocks with 0.2 % of the volume are sampled; each
- * level is tested with every candidate (LIN/CUB x MD/SEQ over the 6 dimension
- * orders = 14) predicting from the ORIGINAL values, and the candidate with the
+/* Uniformly spaced full blocks with 0.2 % of the volume are sampled; each
+ * level is tested with every candidate (LIN/CUB/NAT x MD/SEQ over the 6
+ * dimension orders = 21) predicting from the ORIGINAL values, and the candidate with the
  * smallest aggregated error is kept per level, ties to the lower index.
  * Reading of "aggregated prediction errors": each |x - p| is counted in units
  * of 2*eps/65536, rounded to nearest and capped at 2^36 units, and summed as a
  * 64-bit integer, so the total is exact and does not depend on summation
- * order. Candidate index: spline*7 + (MD ? 0 : 1 + order). */
+ * order. Candidate index: spline*7 + (MD ? 0 : 1 + order).
+ * A full block spans 17 points on every axis of the field, except the flat
+ * axes of 2-D and 1-D fields (size 1), where it spans the one point: 2-D
+ * fields (Sec. 6.1.3) are sampled in 17 x 17 blocks. */
 int orc_tune(const float *x, const uint64_t dims[3], float eps,
-             uint8_t cfg[4][3], uint64_t err[4][14])
+             uint8_t cfg[4][3], uint64_t err[4][ORC_CANDS])
 {
     default_cfg(cfg);
-    memset(err, 0, sizeof(uint64_t) * 4 * 14);
+    memset(err, 0, sizeof(uint64_t) * 4 * ORC_CANDS);
     uint64_t f[3];
-    for (int i = 0; i < 3; i++)
-        f[i] = dims[i] >= SIDE ? (dims[i] - SIDE) / ANCHOR + 1 : 0;
+    int n[3];
+    uint64_t vol = 1;
+    for (int i = 0; i < 3; i++) {
+        n[i] = dims[i] == 1 ? 1 : SIDE; /* block extent: flat axes span 1 point */
+        f[i] = dims[i] == 1 ? 1 : (dims[i] >= SIDE ? (dims[i] - SIDE) / ANCHOR + 1 : 0);
+        vol *= (uint64_t)n[i];
+    }
     uint64_t n_full = f[0] * f[1] * f[2];
     if (n_full == 0)
         return ORC_OK;
     uint64_t N = dims[0] * dims[1] * dims[2];
-    uint64_t n_s = cdiv(2 * N, 1000ull * 4913ull); /* 0.2 % of N in 17^3 blocks */
+    uint64_t n_s = cdiv(2 * N, 1000ull * vol); /* 0.2 % of N in full blocks */
     if (n_s < 1)
         n_s = 1;
     if (n_s > n_full)
@@ -368,25 +381,24 @@ int orc_tune(const float *x, const uint64_t dims[3], float eps,
     float *buf = malloc(sizeof(float) * SIDE * SIDE * SIDE);
     if (!buf)
         return ORC_ERR_NOMEM;
-    int n[3] = {SIDE, SIDE, SIDE};
     for (uint64_t j = 0; j < n_s; j++) {
         uint64_t idx = ((2 * j + 1) * n_full) / (2 * n_s);
         uint64_t c = idx % f[2], b = (idx / f[2]) % f[1], a = idx / (f[1] * f[2]);
-        for (int i0 = 0; i0 < SIDE; i0++)
-            for (int i1 = 0; i1 < SIDE; i1++)
-                for (int i2 = 0; i2 < SIDE; i2++)
-                    buf[(i0 * SIDE + i1) * SIDE + i2] =
+        for (int i0 = 0; i0 < n[0]; i0++)
+            for (int i1 = 0; i1 < n[1]; i1++)
+                for (int i2 = 0; i2 < n[2]; i2++)
+                    buf[(i0 * n[1] + i1) * n[2] + i2] =
                         x[gindex(dims, a * ANCHOR + i0, b * ANCHOR + i1, c * ANCHOR + i2)];
         for (int l = 0; l < 4; l++) {
             int s = 8 >> l;
-            for (int i = 0; i < SIDE; i += s)
-                for (int jj = 0; jj < SIDE; jj += s)
-                    for (int m = 0; m < SIDE; m += s) {
+            for (int i = 0; i < n[0]; i += s)
+                for (int jj = 0; jj < n[1]; jj += s)
+                    for (int m = 0; m < n[2]; m += s) {
                         if (((i / s) & 1) == 0 && ((jj / s) & 1) == 0 && ((m / s) & 1) == 0)
                             continue;
                         int t[3] = {i, jj, m};
-                        float xv = buf[(i * SIDE + jj) * SIDE + m];
-                        for (int cand = 0; cand < 14; cand++) {
+                        float xv = buf[(i * n[1] + jj) * n[2] + m];
+                        for (int cand = 0; cand < ORC_CANDS; cand++) {
                             int spline = cand / 7, r = cand % 7;
                             int scheme = r == 0 ? ORC_MD : ORC_SEQ;
                             int perm = r == 0 ? 0 : r - 1;
@@ -402,7 +414,7 @@ int orc_tune(const float *x, const uint64_t dims[3], float eps,
     free(buf);
     for (int l = 0; l < 4; l++) {
         int best = 0;
-        for (int cand = 1; cand < 14; cand++)
+        for (int cand = 1; cand < ORC_CANDS; cand++)
             if (err[l][cand] < err[l][best])
                 best = cand;
         int r = best % 7;
@@ -1170,7 +1182,7 @@ int orc_compress(const float *x, const uint64_t dims[3], int mode, double eb,
         (prm.reorder != 0 && prm.reorder != 1))
         return ORC_ERR_ARG;
     for (int l = 0; l < 4; l++)
-        if (prm.cfg[l][0] > 1 || prm.cfg[l][1] > 1 || prm.cfg[l][2] > 5)
+        if (prm.cfg[l][0] > 2 || prm.cfg[l][1] > 1 || prm.cfg[l][2] > 5)
             return ORC_ERR_ARG;
 
     const uint64_t N = dims[0] * dims[1] * dims[2];
@@ -1232,7 +1244,7 @@ int orc_compress(const float *x, const uint64_t dims[3], int mode, double eb,
     L.idx_bytes = N < (1ull << 32) ? 4 : 8;
     L.flags = L.idx_bytes == 8 ? 2 : 0;
 
-    uint64_t tune_err[4][14];
+    uint64_t tune_err[4][ORC_CANDS];
     memset(tune_err, 0, sizeof(tune_err));
     if (prm.tune) {
         int rc = orc_tune(x, dims, eps, L.cfg, tune_err);
@@ -1453,7 +1465,7 @@ static int parse_header(const uint8_t *in, uint64_t in_size, layout *L)
     for (int l = 0; l < 4; l++) {
         for (int k = 0; k < 3; k++)
             L->cfg[l][k] = in[56 + 3 * l + k];
-        if (L->cfg[l][0] > 1 || L->cfg[l][1] > 1 || L->cfg[l][2] > 5)
+        if (L->cfg[l][0] > 2 || L->cfg[l][1] > 1 || L->cfg[l][2] > 5)
             return ORC_ERR_CORRUPT;
     }
     L->chunk = get_u32(in + 68);

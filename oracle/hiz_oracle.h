@@ -34,7 +34,10 @@ enum {
 };
 
 enum { ORC_ABS = 0, ORC_REL = 1 };
-enum { ORC_LIN = 0, ORC_CUB = 1 };
+enum { ORC_LIN = 0, ORC_CUB = 1, ORC_NAT = 2 };
+/* tuner candidates: {LIN, CUB, NAT} x {MD, SEQ over the 6 dimension orders};
+ * candidate index = spline * 7 + (MD ? 0 : 1 + order) */
+#define ORC_CANDS 21
 enum { ORC_MD = 0, ORC_SEQ = 1 };
 /* Lossless pipelines (Sec. 5.2.3): Huffman only; TCMS1-BIT1-RRE1 on the codes
  * (no Huffman, the throughput mode); Huffman then RRE4-TCMS8-RZE1 on its
@@ -44,7 +47,7 @@ enum { ORC_PIPE_HF = 0, ORC_PIPE_TP = 1, ORC_PIPE_CR = 2 };
 enum { ORC_FLAG_REORDER = 4 };
 
 /* Per-level interpolation configuration, levels ordered by stride 8, 4, 2, 1.
- * cfg[l][0] = spline (ORC_LIN/ORC_CUB), cfg[l][1] = scheme (ORC_MD/ORC_SEQ),
+ * cfg[l][0] = spline (ORC_LIN/ORC_CUB/ORC_NAT), cfg[l][1] = scheme (ORC_MD/ORC_SEQ),
  * cfg[l][2] = dimension order index 0..5 for SEQ:
  * 0 (x,y,z) 1 (x,z,y) 2 (y,x,z) 3 (y,z,x) 4 (z,x,y) 5 (z,y,x). */
 typedef struct {
@@ -61,7 +64,7 @@ typedef struct {
     float *recon;          /* N reconstructed values x' the compressor kept */
     uint64_t hist[256];    /* code histogram */
     uint8_t cfg[4][3];     /* configuration written to the header */
-    uint64_t tune_err[4][14]; /* tuner error sums (when tuned) */
+    uint64_t tune_err[4][ORC_CANDS]; /* tuner error sums (when tuned) */
     float eps;             /* absolute bound actually used */
     uint64_t n_out;        /* number of outliers */
 } orc_debug;
@@ -83,7 +86,7 @@ float orc_predict(const float *buf, const int n[3], const int t[3], int s,
 
 /* Sampled-block tuner (Sec. 5.1.3). */
 int orc_tune(const float *x, const uint64_t dims[3], float eps,
-             uint8_t cfg[4][3], uint64_t err[4][14]);
+             uint8_t cfg[4][3], uint64_t err[4][ORC_CANDS]);
 
 /* Canonical Huffman codebook from a 256-bin histogram. */
 int orc_codebook(const uint64_t hist[256], uint8_t len[256], uint32_t code[256]);

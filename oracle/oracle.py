@@ -17,7 +17,8 @@ SRC = os.path.join(HERE, "hiz_oracle.c")
 
 OK, ERR_ARG, ERR_NONFINITE, ERR_BUFSZ, ERR_CORRUPT, ERR_NOMEM = 0, 1, 2, 3, 4, 5
 ABS, REL = 0, 1
-LIN, CUB = 0, 1
+LIN, CUB, NAT = 0, 1, 2
+CANDS = 21  # tuner candidates: {LIN, CUB, NAT} x {MD, SEQ x 6 orders}
 MD, SEQ = 0, 1
 PIPE_HF, PIPE_TP, PIPE_CR = 0, 1, 2
 FLAG_REORDER = 4
@@ -45,7 +46,7 @@ class Params(C.Structure):
 
 class Debug(C.Structure):
     _fields_ = [("codes", C.c_void_p), ("recon", C.c_void_p), ("hist", C.c_uint64 * 256),
-                ("cfg", (C.c_uint8 * 3) * 4), ("tune_err", (C.c_uint64 * 14) * 4),
+                ("cfg", (C.c_uint8 * 3) * 4), ("tune_err", (C.c_uint64 * CANDS) * 4),
                 ("eps", C.c_float), ("n_out", C.c_uint64)]
 
 
@@ -141,7 +142,7 @@ DEFAULT_CFG = ((CUB, MD, 0),) * 4
 def tune(x: np.ndarray, eps_value):
     x = np.ascontiguousarray(x, dtype=np.float32)
     cfg = ((C.c_uint8 * 3) * 4)()
-    err = np.zeros((4, 14), dtype=np.uint64)
+    err = np.zeros((4, CANDS), dtype=np.uint64)
     rc = lib().orc_tune(x.ctypes.data, _dims(x.shape), float(eps_value), C.byref(cfg),
                         err.ctypes.data)
     if rc:
@@ -234,7 +235,7 @@ def compress(x: np.ndarray, mode, eb, tune=True, cfg=DEFAULT_CFG, chunk=1024,
     finally:
         lib().orc_free(out)
     hist = np.frombuffer(bytes(dbg.hist), dtype=np.uint64).copy()
-    terr = np.frombuffer(bytes(dbg.tune_err), dtype=np.uint64).reshape(4, 14).copy()
+    terr = np.frombuffer(bytes(dbg.tune_err), dtype=np.uint64).reshape(4, CANDS).copy()
     return Result(stream, codes, recon, hist, cfg_tuple(dbg.cfg), np.float32(dbg.eps),
                   int(dbg.n_out), terr)
 

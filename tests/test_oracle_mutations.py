@@ -21,10 +21,10 @@ MUTATIONS = {
     "sample_index": ("uint64_t idx = ((2 * j + 1) * n_full) / (2 * n_s);",
                      "uint64_t idx = (j * n_full) / n_s;"),
     # 2 % of the volume instead of 0.2 %
-    "sample_count": ("cdiv(2 * N, 1000ull * 4913ull)", "cdiv(20 * N, 1000ull * 4913ull)"),
+    "sample_count": ("cdiv(2 * N, 1000ull * vol)", "cdiv(20 * N, 1000ull * vol)"),
     # rounding the sample count down instead of up
-    "sample_count_floor": ("uint64_t n_s = cdiv(2 * N, 1000ull * 4913ull);",
-                           "uint64_t n_s = (2 * N) / (1000ull * 4913ull);"),
+    "sample_count_floor": ("uint64_t n_s = cdiv(2 * N, 1000ull * vol);",
+                           "uint64_t n_s = (2 * N) / (1000ull * vol);"),
     # ties to the higher candidate index
     "tie_rule": ("if (err[l][cand] < err[l][best])", "if (err[l][cand] <= err[l][best])"),
     # error units truncated instead of rounded to nearest
@@ -59,7 +59,7 @@ def _tune_with(L):
     def tune(x, eps):
         x = np.ascontiguousarray(x, dtype=np.float32)
         cfg = ((C.c_uint8 * 3) * 4)()
-        err = np.zeros((4, 14), dtype=np.uint64)
+        err = np.zeros((4, OO.CANDS), dtype=np.uint64)
         dims = (C.c_uint64 * 3)(*x.shape)
         rc = L.orc_tune(x.ctypes.data, dims, float(eps), C.byref(cfg), err.ctypes.data)
         assert rc == 0

@@ -535,3 +535,37 @@ def test_huffman_tie_rule_golden(golden_dir):
     hist[g["symbols"]] = g["counts"]
     ln, _ = O.codebook(hist)
     assert [int(ln[s]) for s in g["symbols"]] == g["lengths"]
+
+
+# ---------------------------------------------------------------------------
+# Natural cubic spline candidate (Sec. 5.1.3, "multiple interpolation splines")
+# ---------------------------------------------------------------------------
+
+def test_natural_spline_matches_scipy():
+    # the natural cubic spline through the samples at -3s, -s, s, 3s (zero
+    # second derivative at the outer two), evaluated at the midpoint, as
+    # scipy's CubicSpline(bc_type="natural") computes it
+    from scipy.interpolate import CubicSpline
+    rng = np.random.default_rng(77)
+    for _ in range(200):
+        a, b, c, d = rng.uniform(-4, 4, 4).astype(np.float32)
+        want = CubicSpline([-3.0, -1.0, 1.0, 3.0], np.array([a, b, c, d], np.float64),
+                           bc_type="natural")(0.0)
+        got, rank = O.stencil(O.NAT, a, b, c, d, True, True, True)
+        assert rank == 4
+        assert abs(float(got) - float(want)) <= 4 * np.spacing(np.float32(abs(want) + 8))
+
+
+def test_natural_spline_exact_cases():
+    # weights (-3, 23, 23, -3) / 40: a line is reproduced, a parabola is not
+    for (a, b, c, d) in [(-3.0, -1.0, 1.0, 3.0), (10.0, 14.0, 18.0, 22.0)]:
+        got, _ = O.stencil(O.NAT, a, b, c, d, True, True, True)
+        assert got == np.float32((b + c) / 2)
+    got, _ = O.stencil(O.NAT, 9.0, 1.0, 1.0, 9.0, True, True, True)  # x^2 at -3, -1, 1, 3
+    assert got == np.float32(-0.2)
+    # without all four samples it falls back exactly like the cubic
+    for pa, pc, pd in [(False, True, True), (True, True, False), (False, True, False),
+                       (True, False, False), (False, False, False)]:
+        n = O.stencil(O.NAT, 2.0, 3.0, 7.0, 5.0, pa, pc, pd)
+        cb = O.stencil(O.CUB, 2.0, 3.0, 7.0, 5.0, pa, pc, pd)
+        assert n == cb

@@ -92,13 +92,21 @@ def check_tuner(tune):
     for l in range(4):
         if not np.array_equal(err[l, :7], want[l]):
             fails.append(f"level {l}: linear sums {err[l, :7].tolist()} != {want[l].tolist()}")
-    # cubic candidates: linear at stride 8 (no third sample in a full block),
-    # exact at strides 4, 2, 1
-    if not np.array_equal(err[0, 7:], want[0]):
-        fails.append(f"stride 8 cubic sums {err[0, 7:].tolist()} != {want[0].tolist()}")
+    # cubic and natural-spline candidates: linear at stride 8 (no third sample
+    # in a full block); the cubic is exact at strides 4, 2, 1
+    for lo in (7, 14):
+        if not np.array_equal(err[0, lo:lo + 7], want[0]):
+            fails.append(f"stride 8 sums {err[0, lo:lo + 7].tolist()} != {want[0].tolist()}")
     for l in (1, 2, 3):
-        if np.any(err[l, 7:] != 0):
-            fails.append(f"level {l}: cubic sums {err[l, 7:].tolist()} not all 0")
+        if np.any(err[l, 7:14] != 0):
+            fails.append(f"level {l}: cubic sums {err[l, 7:14].tolist()} not all 0")
+    # natural spline, SEQ(y,z,x) (index 18): along x it misses a quadratic by
+    # 0.2*K*s^2 where all four samples exist, i.e. only at x = 6, 10 of stride
+    # 2 (9.6 = 1.2 units -> 1); elsewhere the one-sided quadratics are exact.
+    # 2 x-values x 9 x 9 targets x 2 blocks = 324 units at stride 2.
+    # at stride 1 the interior miss is 2.4 = 0.3 units, which rounds to 0
+    if err[1, 18] != 0 or err[2, 18] != 324 or err[3, 18] != 0:
+        fails.append(f"natural-spline SEQ(y,z,x) sums {err[:, 18].tolist()}")
     # stride 8: SEQ(x,y,z) and SEQ(x,z,y) tie (and so do their cubic twins):
     # the lowest index, 1, wins. Strides 4, 2, 1: the seven zeros tie: index 7.
     want_cfg = ((O.LIN, O.SEQ, 0), (O.CUB, O.MD, 0), (O.CUB, O.MD, 0), (O.CUB, O.MD, 0))
@@ -113,8 +121,33 @@ def check_tuner(tune):
     err = np.asarray(err, dtype=np.int64)
     if not np.array_equal(err[:, :7], expected_lin_sums(1)):
         fails.append(f"81^3: linear sums {err[:, :7].tolist()}")
-    if np.any(err[1:, 7:] != 0):
+    if np.any(err[1:, 7:14] != 0):
         fails.append("81^3: cubic sums not 0")
+
+    # A 2-D field (flat x axis): blocks of 17 x 17 points, 0.2 % of N is
+    # 0.16 blocks of 289 -> 1 sample, at floor(0.5 * 90) = 45 of the 10 x 9
+    # grid of full 2-D blocks = (0, 5, 0). The quadratic now runs along y:
+    # SEQ orders with z after y predict {y, z} targets along z (exact), the
+    # others along y.
+    shape = (1, 161, 145)
+    rng = np.random.default_rng(8)
+    x = rng.integers(0, 1 << 18, size=shape).astype(np.float32)
+    Y = np.arange(80, 97, dtype=np.float64)[:, None]
+    x[0, 80:97, 0:17] = ((C0 + K * Y * Y) * np.ones((1, 17))).astype(np.float32)
+    cfg, err = tune(x, EPS)
+    err = np.asarray(err, dtype=np.int64)
+    for l, s_ in enumerate((8, 4, 2, 1)):
+        o, e, a = _oea(s_)
+        miss = K * s_ * s_
+        oe, oa = o * e * _units(miss), o * a * _units(miss)
+        md = o * e * _units(miss) + o * o * _units(miss / 2)
+        want2 = [md, oe, oa, oe, oe, oa, oa]
+        if err[l, :7].tolist() != want2:
+            fails.append(f"2-D level {l}: linear sums {err[l, :7].tolist()} != {want2}")
+        if l > 0 and np.any(err[l, 7:14] != 0):
+            fails.append(f"2-D level {l}: cubic sums not 0")
+    if tuple(tuple(int(v) for v in c) for c in cfg) != want_cfg:
+        fails.append(f"2-D picks {cfg}")
 
     # No full block (a side below 17): the default, cubic + MD everywhere.
     x = np.random.default_rng(7).standard_normal((40, 16, 40)).astype(np.float32)
