@@ -51,13 +51,18 @@ typedef enum {
 typedef enum { HIZ_ABS = 0, HIZ_REL = 1 } hiz_eb_mode;
 
 /* Interpolation choices of one level (Sec. 5.1.2). */
-enum { HIZ_SPLINE_LINEAR = 0, HIZ_SPLINE_CUBIC = 1 };
+/* LINEAR: (1,1)/2; CUBIC: Lagrange (-1,9,9,-1)/16; NATURAL: the natural cubic
+ * spline through the four samples, (-3,23,23,-3)/40 (Sec. 5.1.3, "multiple
+ * interpolation splines"). Where samples are missing, CUBIC and NATURAL fall
+ * back to one-sided quadratics, linear, extrapolation, copy. */
+enum { HIZ_SPLINE_LINEAR = 0, HIZ_SPLINE_CUBIC = 1, HIZ_SPLINE_NATURAL = 2 };
 enum { HIZ_SCHEME_MD = 0, HIZ_SCHEME_SEQ = 1 };
 /* SEQ dimension orders: 0 (x,y,z) 1 (x,z,y) 2 (y,x,z) 3 (y,z,x) 4 (z,x,y) 5 (z,y,x). */
 
 typedef struct {
     /* 1 (default): pick each level's spline and scheme with the sampled-block
-     * tuner of Sec. 5.1.3; 0: use `level_cfg`. */
+     * tuner of Sec. 5.1.3 (21 candidates: 3 splines x {MD, SEQ over the 6
+     * dimension orders}); 0: use `level_cfg`. */
     int tune;
     /* Per level, strides 8, 4, 2, 1: {spline, scheme, order}. */
     uint8_t level_cfg[4][3];
@@ -67,7 +72,18 @@ typedef struct {
     /* Cells along z per GPU tile (1, 2 or 4); 0 = default. Does not change the
      * output. */
     uint32_t tile_z;
+    /* Lossless pipeline (Sec. 5.2.3): HIZ_PIPE_HUFFMAN (default) Huffman
+     * coding of the codes; HIZ_PIPE_TP the throughput mode, the stages
+     * TCMS1-BIT1-RRE1 straight on the codes (no Huffman); HIZ_PIPE_CR the
+     * ratio mode, Huffman then RRE4-TCMS8-RZE1 on its payload. The stages run
+     * on 16 KiB chunks; a chunk they cannot shrink is stored raw. */
+    uint32_t pipeline;
+    /* Codes reordered by interpolation level (Sec. 5.1.4, Eq. reorder) before
+     * the lossless stage: 1 on, 0 off, -1 the pipeline's default (on for
+     * HIZ_PIPE_CR, off otherwise). Recorded in the stream. */
+    int32_t reorder;
 } hiz_params;
+enum { HIZ_PIPE_HUFFMAN = 0, HIZ_PIPE_TP = 1, HIZ_PIPE_CR = 2 };
 
 /* Header view of a stream (host-side parse; see hiz_inspect). */
 typedef struct {
@@ -83,6 +99,9 @@ typedef struct {
     uint64_t n_chunks;
     uint64_t payload_words;
     uint64_t total_bytes;
+    int pipeline;       /* HIZ_PIPE_* */
+    int reorder;        /* 1: codes reordered by level */
+    uint64_t lc_bytes;  /* bytes stored by the last stages (HIZ_PIPE_TP / _CR) */
 } hiz_info;
 
 /* Create a context on HIP device `device`. `workspace_bytes` reserves device

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhiz.so")
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["k_prep.hip", "k_interp.hip", "k_huff.hip", "runtime.hip", "server.hip"]
+SOURCES = ["k_prep.hip", "k_interp.hip", "k_huff.hip", "k_lc.hip", "runtime.hip", "server.hip"]
 ARCH = os.environ.get("HIZ_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

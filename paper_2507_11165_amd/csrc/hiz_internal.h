@@ -3,6 +3,8 @@
 // kernels write, and the host-side launchers of every kernel.
 #pragma once
 
+#include "hiz.h"
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -13,7 +15,7 @@ constexpr int kAnchor = 16;
 constexpr int kSide = 17;
 constexpr int kLevels = 4;      // strides 8, 4, 2, 1
 constexpr int kMaxCodeLen = 32; // Huffman length cap
-constexpr int kCands = 14;      // tuner candidates: {LIN, CUB} x {MD, SEQ x 6 orders}
+constexpr int kCands = 21;      // tuner candidates: {LIN, CUB, NAT} x {MD, SEQ x 6 orders}
 
 // ---- stream layout (the paper leaves the container open; this one is ours) ----
 constexpr uint32_t kMagic = 0x315A4948u; // "HIZ1"
@@ -25,8 +27,14 @@ constexpr int kOffChunks = 384; // u32 words per chunk [n_chunks]
 constexpr int H_MAGIC = 0, H_VERSION = 4, H_MODE = 6, H_FLAGS = 7, H_DIMS = 8, H_EB = 32,
               H_EPS = 40, H_MIN = 44, H_MAX = 48, H_ASTRIDE = 52, H_NLEV = 53, H_CFG = 56,
               H_CHUNK = 68, H_NOUT = 72, H_PWORDS = 80, H_TOTAL = 88, H_NCHUNKS = 96,
-              H_NANCH = 104;
-constexpr uint8_t kFlagConst = 1, kFlagIdx64 = 2;
+              H_NANCH = 104, H_PIPE = 54, H_LCBYTES = 112, H_NLC = 120;
+constexpr uint8_t kFlagConst = 1, kFlagIdx64 = 2, kFlagReorder = 4;
+
+// Lossless pipelines (Sec. 5.2.3): Huffman only; TCMS1-BIT1-RRE1 straight on
+// the codes (throughput mode); Huffman, then RRE4-TCMS8-RZE1 on its payload
+// (ratio mode). The bitwise-redundancy stages run on chunks of kLcChunk bytes.
+enum : uint8_t { PIPE_HF = 0, PIPE_TP = 1, PIPE_CR = 2 };
+constexpr int kLcChunk = 16384;
 
 __host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15u) & ~uint64_t(15); }
 __host__ __device__ inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -70,6 +78,7 @@ struct FieldState {
     uint8_t cfg[kLevels][3];
     uint8_t pad2[4];
     uint64_t off_oidx, off_oval, off_payload;
+    uint64_t lc_bytes;   // bytes the bitwise-redundancy stages stored
     uint64_t hist[256];
     uint64_t tune_err[kLevels][kCands];
     uint32_t cb_code[256];
@@ -119,6 +128,20 @@ struct Job {
     uint64_t off_oidx, off_oval, off_payload, n_out, payload_words;
     float eps;
     uint32_t pad2;
+    // lossless pipeline and code order
+    uint8_t pipe;        // PIPE_*
+    uint8_t reorder;     // 1: the lossless stage sees the codes reordered by level
+    uint8_t pad4[6];
+    uint8_t *seq;        // codes in the order the lossless stage sees (== codes if not reordered)
+    uint8_t *hpay;       // ratio mode: Huffman payload in the workspace
+    uint64_t hpay_cap;   // its capacity in bytes
+    uint64_t *lb_c;      // look-back status words: bitwise-redundancy chunks (stored bytes)
+    uint64_t *lb_d;      // look-back status words: outlier units / bitwise-redundancy chunks (outliers)
+    uint64_t lc_begin, n_lc;   // bitwise-redundancy chunks: work-list prefix, chunks (an upper
+                               // bound when compressing the Huffman payload, whose size the
+                               // device finds)
+    uint64_t ou_begin, n_ou;   // outlier units of kLcChunk codes (compression, separate pass)
+    uint64_t off_lcsizes, off_lcdata, lc_bytes; // decompression: from the header
 };
 
 // Work list shared by a launch: njobs fields and their concatenated units.
@@ -133,11 +156,13 @@ struct Counters {
     uint32_t enc_next;
     uint32_t dec_next;
     uint32_t tile_next[8]; // per XCD: tiles claimed by predict / reconstruct
-    uint32_t pad[6];
+    uint32_t lc_next;      // bitwise-redundancy chunks
+    uint32_t ou_next;      // outlier units
+    uint32_t pad[4];
 };
 
 // ---- kernel launchers (each defined next to its kernel) ----
-enum WorkKind { WK_MM, WK_TUNE, WK_TILE, WK_CHUNK, WK_GROUP, WK_DBLK, WK_OUT };
+enum WorkKind { WK_MM, WK_TUNE, WK_TILE, WK_CHUNK, WK_GROUP, WK_DBLK, WK_OUT, WK_LC, WK_OU };
 constexpr int kEncGroupChunks = 64; // chunks per workgroup of the encoder's sizing pass
 
 void launch_init_compress(const Job *d_jobs, int njobs, uint64_t max_chunks, Counters *cnt,
@@ -174,7 +199,20 @@ uint64_t coarse_codes_per_tile(int tile_z);
 // its header is read): hiz_workspace_bound of an n x 1 x 1 field plus the
 // most pre-pass slots any shape of n points can have.
 uint64_t workspace_bound_points(uint64_t n);
+// Serving helpers (runtime.hip): pinned staging reserved for batches of up to
+// n fields; decompression submit with each stream's first kOffChunks bytes
+// already copied to the host (nothing waits for the device).
+hiz_status ctx_reserve_pinned(hiz_ctx *c, int n);
+hiz_status ctx_decompress_submit_hdrs(hiz_ctx *c, int n, const void *const *d_ins,
+                                      const uint64_t *in_sizes, float *const *d_fields,
+                                      const uint64_t *field_caps, hipStream_t s,
+                                      const uint8_t *h_hdrs);
 int reconstruct_blocks_per_cu(int tile_z);
+// Bitwise-redundancy stages, reordering and outliers (k_lc.hip).
+void launch_reorder(const Job *d_jobs, int njobs, uint64_t max_n, bool inverse, hipStream_t s);
+void launch_outliers(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, hipStream_t s);
+void launch_lc_encode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, hipStream_t s);
+void launch_lc_decode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, hipStream_t s);
 
 // ---- device helpers shared by the kernels ----
 #ifdef __HIPCC__
@@ -257,6 +295,8 @@ __device__ inline uint64_t job_begin(const Job &j)
     case WK_CHUNK: return j.chunk_begin;
     case WK_GROUP: return j.group_begin;
     case WK_DBLK: return j.dblk_begin;
+    case WK_LC: return j.lc_begin;
+    case WK_OU: return j.ou_begin;
     default: return j.out_begin;
     }
 }
@@ -320,6 +360,108 @@ __device__ inline void reduce_partials(const uint2 *p, uint64_t n, uint32_t &kmn
         }
     }
     block_minmax(kmn, kmx, red);
+}
+
+// ---------------------------------------------------------------------------
+// Look-back status words: [2-bit flag | 62-bit value]; flag 1 = the unit's own
+// aggregate, 2 = inclusive prefix through the unit. Each unit publishes its
+// aggregate, walks back over predecessors until an inclusive prefix, then
+// publishes its own inclusive prefix. Units are handed out in increasing order
+// by an atomic counter, so every predecessor is already running.
+// ---------------------------------------------------------------------------
+constexpr uint64_t LB_AGG = 1ull << 62, LB_INC = 2ull << 62, LB_MASK = (1ull << 62) - 1;
+
+__device__ inline uint64_t lb_load(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void lb_store(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t shfl64(uint64_t v, int src)
+{
+    uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t wave_sum64(uint64_t v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int o = 32; o > 0; o >>= 1)
+        v += shfl64(v, lane ^ o);
+    return v;
+}
+
+// Exclusive prefix of unit `idx` (called by all 64 lanes of one wave). The
+// wave reads the statuses of 64 predecessors per round trip; it stops at the
+// nearest inclusive prefix once every unit between is at least published.
+__device__ inline uint64_t lookback(uint64_t *arr, uint64_t idx, uint64_t agg)
+{
+    const int lane = threadIdx.x & 63;
+    if (idx == 0) {
+        if (lane == 0)
+            lb_store(&arr[0], LB_INC | agg);
+        return 0;
+    }
+    if (lane == 0)
+        lb_store(&arr[idx], LB_AGG | agg);
+    uint64_t excl = 0;
+    int64_t end = (int64_t)idx;
+    for (;;) {
+        const int64_t j = end - 1 - lane;
+        const uint64_t w = j >= 0 ? lb_load(&arr[j]) : LB_INC; // before unit 0: inclusive 0
+        const uint64_t f = w >> 62;
+        const uint64_t inc = __ballot(f == 2);
+        const uint64_t empty = __ballot(f == 0);
+        if (inc) {
+            const int p = __ffsll((unsigned long long)inc) - 1;
+            const uint64_t need = (p == 63) ? ~0ull : ((2ull << p) - 1);
+            if ((empty & need) == 0) {
+                excl += wave_sum64(lane <= p ? (w & LB_MASK) : 0);
+                break;
+            }
+        } else if (empty == 0) {
+            excl += wave_sum64(w & LB_MASK);
+            end -= 64;
+            continue;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0)
+        lb_store(&arr[idx], LB_INC | (excl + agg));
+    return excl;
+}
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = (uint32_t)__shfl_up((int)v, o, 64);
+        if (lane >= o)
+            v += u;
+    }
+    return v;
+}
+
+__device__ inline uint64_t wave_incl_scan64(uint64_t v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, o, 64);
+        uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), o, 64);
+        if (lane >= o)
+            v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+__device__ inline void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Ordered 32-bit key of a float: unsigned order == total order (-0 < +0).

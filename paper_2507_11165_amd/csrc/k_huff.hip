@@ -7,108 +7,6 @@
 
 namespace hiz {
 
-// ---------------------------------------------------------------------------
-// Look-back status words: [2-bit flag | 62-bit value]; flag 1 = the unit's own
-// aggregate, 2 = inclusive prefix through the unit. Each unit publishes its
-// aggregate, walks back over predecessors until an inclusive prefix, then
-// publishes its own inclusive prefix. Units are handed out in increasing order
-// by an atomic counter, so every predecessor is already running.
-// ---------------------------------------------------------------------------
-constexpr uint64_t LB_AGG = 1ull << 62, LB_INC = 2ull << 62, LB_MASK = (1ull << 62) - 1;
-
-__device__ inline uint64_t lb_load(const uint64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void lb_store(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline uint64_t shfl64(uint64_t v, int src)
-{
-    uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
-    uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ inline uint64_t wave_sum64(uint64_t v)
-{
-    const int lane = threadIdx.x & 63;
-    for (int o = 32; o > 0; o >>= 1)
-        v += shfl64(v, lane ^ o);
-    return v;
-}
-
-// Exclusive prefix of unit `idx` (called by all 64 lanes of one wave). The
-// wave reads the statuses of 64 predecessors per round trip; it stops at the
-// nearest inclusive prefix once every unit between is at least published.
-__device__ uint64_t lookback(uint64_t *arr, uint64_t idx, uint64_t agg)
-{
-    const int lane = threadIdx.x & 63;
-    if (idx == 0) {
-        if (lane == 0)
-            lb_store(&arr[0], LB_INC | agg);
-        return 0;
-    }
-    if (lane == 0)
-        lb_store(&arr[idx], LB_AGG | agg);
-    uint64_t excl = 0;
-    int64_t end = (int64_t)idx;
-    for (;;) {
-        const int64_t j = end - 1 - lane;
-        const uint64_t w = j >= 0 ? lb_load(&arr[j]) : LB_INC; // before unit 0: inclusive 0
-        const uint64_t f = w >> 62;
-        const uint64_t inc = __ballot(f == 2);
-        const uint64_t empty = __ballot(f == 0);
-        if (inc) {
-            const int p = __ffsll((unsigned long long)inc) - 1;
-            const uint64_t need = (p == 63) ? ~0ull : ((2ull << p) - 1);
-            if ((empty & need) == 0) {
-                excl += wave_sum64(lane <= p ? (w & LB_MASK) : 0);
-                break;
-            }
-        } else if (empty == 0) {
-            excl += wave_sum64(w & LB_MASK);
-            end -= 64;
-            continue;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    if (lane == 0)
-        lb_store(&arr[idx], LB_INC | (excl + agg));
-    return excl;
-}
-
-__device__ inline uint32_t wave_incl_scan(uint32_t v)
-{
-    const int lane = threadIdx.x & 63;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t u = (uint32_t)__shfl_up((int)v, o, 64);
-        if (lane >= o)
-            v += u;
-    }
-    return v;
-}
-
-__device__ inline uint64_t wave_incl_scan64(uint64_t v)
-{
-    const int lane = threadIdx.x & 63;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, o, 64);
-        uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), o, 64);
-        if (lane >= o)
-            v += ((uint64_t)hi << 32) | lo;
-    }
-    return v;
-}
-
-__device__ inline void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-}
-
 template <typename T> __device__ inline void put_le(uint8_t *p, T v)
 {
     __builtin_memcpy(p, &v, sizeof(T));
@@ -149,6 +47,7 @@ __device__ void write_header(uint8_t *h, const Job &J, uint8_t flags, float eps,
     put_le<uint64_t>(h + H_TOTAL, total);
     put_le<uint64_t>(h + H_NCHUNKS, n_chunks);
     put_le<uint64_t>(h + H_NANCH, n_anchors);
+    h[H_PIPE] = (flags & kFlagConst) ? (uint8_t)PIPE_HF : J.pipe;
 }
 
 __global__ __launch_bounds__(256) void k_codebook(const Job *__restrict__ jobs, int njobs)
@@ -211,7 +110,8 @@ __global__ __launch_bounds__(256) void k_codebook(const Job *__restrict__ jobs, 
         return;
     }
 
-    cnt[t] = st->hist[t];
+    // throughput mode: no Huffman stage, every code length 0
+    cnt[t] = J.pipe == PIPE_TP ? 0 : st->hist[t];
     for (;;) {
         __syncthreads();
         const uint64_t c = cnt[t];
@@ -323,7 +223,8 @@ __global__ __launch_bounds__(256) void k_codebook(const Job *__restrict__ jobs, 
     // layout of the variable sections and the header
     const uint64_t n_out = st->hist[0];
     const uint64_t ib = J.idx_bytes;
-    const uint64_t end_chunks = kOffChunks + 4 * J.n_chunks;
+    // the table at 384: Huffman word counts, or the stage chunk sizes (throughput mode)
+    const uint64_t end_chunks = kOffChunks + 4 * (J.pipe == PIPE_TP ? J.n_lc : J.n_chunks);
     const uint64_t end_anch = J.off_anchors + 4 * J.n_anchors;
     const uint64_t o_idx = align16(end_anch);
     const uint64_t end_idx = o_idx + ib * n_out;
@@ -340,8 +241,8 @@ __global__ __launch_bounds__(256) void k_codebook(const Job *__restrict__ jobs, 
         st->off_payload = o_pay;
         st->vmin = vmin;
         st->vmax = vmax;
-        write_header(hdr, J, ib == 8 ? kFlagIdx64 : 0, st->eps, vmin, vmax, s_cfg, n_out,
-                     J.n_chunks, J.n_anchors, 0);
+        write_header(hdr, J, (uint8_t)((ib == 8 ? kFlagIdx64 : 0) | (J.reorder ? kFlagReorder : 0)),
+                     st->eps, vmin, vmax, s_cfg, n_out, J.n_chunks, J.n_anchors, 0);
     }
     __syncthreads();
     if (t < kHdrBytes / 4 && 4 * (uint64_t)t + 4 <= cap)
@@ -458,7 +359,7 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
             const int P = (sl + 63) / 64;
             const int n = max(0, min(P, sl - lane * P));
             uint32_t r[4], b, z;
-            load_lane_codes(gmem(J.codes) + c0 + sg * kEncSeg + lane * P, P, n, r);
+            load_lane_codes(gmem(J.seq) + c0 + sg * kEncSeg + lane * P, P, n, r);
             lane_sizes(r, n, len, b, z);
             bits += b;
             zeros += z;
@@ -491,15 +392,18 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
     }
     if (lane == 0 && cfirst + nc == J.n_chunks) {
         const uint64_t pw = wbase + gw;
-        const uint64_t total_bytes = st->off_payload + 4 * pw;
         st->payload_words = pw;
-        st->total_bytes = total_bytes;
-        if (H_TOTAL + 8 <= cap) {
+        if (H_TOTAL + 8 <= cap)
             *reinterpret_cast<uint64_t *>(J.stream + H_PWORDS) = pw;
-            *reinterpret_cast<uint64_t *>(J.stream + H_TOTAL) = total_bytes;
+        if (J.pipe == PIPE_HF) {
+            // the ratio mode's stream ends after its last stages (sized there)
+            const uint64_t total_bytes = st->off_payload + 4 * pw;
+            st->total_bytes = total_bytes;
+            if (H_TOTAL + 8 <= cap)
+                *reinterpret_cast<uint64_t *>(J.stream + H_TOTAL) = total_bytes;
+            if (total_bytes > cap)
+                atomicOr(&st->flags, (uint32_t)ST_OVERFLOW);
         }
-        if (total_bytes > cap)
-            atomicOr(&st->flags, (uint32_t)ST_OVERFLOW);
         if (zbase + gz != st->n_out)
             atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
     }
@@ -536,14 +440,21 @@ __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, 
         const uint64_t ck = id - J.chunk_begin;
         const uint64_t c0 = ck << J.log2_chunk;
         const int clen = (int)(min(c0 + J.chunk, J.N) - c0);
-        HIZ_GLOBAL const uint8_t *src = gmem(J.codes) + c0;
+        HIZ_GLOBAL const uint8_t *src = gmem(J.seq) + c0;
         HIZ_GLOBAL uint8_t *stream = gmem(J.stream);
         HIZ_GLOBAL const float *field = gmem(J.field);
         const uint64_t wbase = gmem(J.woff)[ck];
         uint64_t zpos0 = gmem(J.zoff)[ck];
         const uint64_t cap = J.cap;
-        HIZ_GLOBAL uint32_t *payload = reinterpret_cast<HIZ_GLOBAL uint32_t *>(stream + st->off_payload);
-        const uint64_t pay_words_cap = cap > st->off_payload ? (cap - st->off_payload) / 4 : 0;
+        // the payload goes to the stream, or (ratio mode) to the workspace for the last stages
+        const bool cr = J.pipe == PIPE_CR;
+        HIZ_GLOBAL uint32_t *payload =
+            cr ? reinterpret_cast<HIZ_GLOBAL uint32_t *>(gmem(J.hpay))
+               : reinterpret_cast<HIZ_GLOBAL uint32_t *>(stream + st->off_payload);
+        const uint64_t pay_words_cap =
+            cr ? J.hpay_cap / 4 : (cap > st->off_payload ? (cap - st->off_payload) / 4 : 0);
+        // outliers here only when these codes are in row-major order
+        const bool outl = !J.reorder;
         const uint64_t o_idx = st->off_oidx, o_val = st->off_oval;
         const int ib = J.idx_bytes;
         uint64_t sb = 0; // chunk-relative bit at the segment start
@@ -586,7 +497,7 @@ __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, 
                     curw = cd << (32 - rr);
                     sh = rr;
                 }
-                if (c == 0) {
+                if (c == 0 && outl) {
                     const uint64_t gi = gfirst + k;
                     if (o_idx + (zpos + 1) * ib <= cap) {
                         if (ib == 4)
@@ -677,6 +588,8 @@ __global__ __launch_bounds__(256) void k_init_decompress(const Job *__restrict__
     }
     for (uint64_t i = blockIdx.x * 256ull + t; i < J.n_dblk; i += 256ull * gridDim.x)
         J.lb_a[i] = 0;
+    for (uint64_t i = blockIdx.x * 256ull + t; i < J.n_lc; i += 256ull * gridDim.x)
+        J.lb_c[i] = 0;
 }
 
 void launch_init_decompress(const Job *d_jobs, int njobs, uint64_t max_blocks, Counters *cnt,
@@ -830,9 +743,11 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     }
     if (chunk == J.n_chunks - 1 && start + wc != pw)
         atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
+    // the payload: in the stream, or (ratio mode) restored by the last stages
     HIZ_GLOBAL const uint32_t *words =
-        reinterpret_cast<HIZ_GLOBAL const uint32_t *>(gmem(J.stream) + J.off_payload);
-    HIZ_GLOBAL uint8_t *codes = gmem(J.codes);
+        J.pipe == PIPE_CR ? reinterpret_cast<HIZ_GLOBAL const uint32_t *>(gmem(J.hpay))
+                          : reinterpret_cast<HIZ_GLOBAL const uint32_t *>(gmem(J.stream) + J.off_payload);
+    HIZ_GLOBAL uint8_t *codes = gmem(J.seq);
     const uint64_t i0 = chunk << J.log2_chunk, i1 = min(i0 + J.chunk, J.N);
     const uint32_t nsym = (uint32_t)(i1 - i0);
     const uint32_t maxlen = s_maxlen;

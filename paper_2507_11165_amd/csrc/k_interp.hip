@@ -58,17 +58,29 @@ template <int B, int E, typename F> __device__ __forceinline__ void static_for(F
     }
 }
 
+// Four-sample midpoint value of the cubic splines (CUB = 1: Lagrange
+// (-1, 9, 9, -1) / 16; CUB = 2: the natural cubic spline through the samples,
+// zero second derivative at the outer two, (-3, 23, 23, -3) / 40).
+template <int CUB> __device__ __forceinline__ float mid4(float a, float b, float c, float d)
+{
+    if constexpr (CUB == 2)
+        return ((b + c) * 23.0f - (a + d) * 3.0f) / 40.0f;
+    else
+        return ((b + c) * 9.0f - (a + d)) * 0.0625f;
+}
+
 // 1-D spline stencil (Sec. 5.1.2) from the samples a = v(t-3s), b = v(t-s),
-// c = v(t+s), d = v(t+3s): Lagrange weights at the midpoint; where samples are
-// missing the order drops to quadratic (one side), linear, linear
-// extrapolation or copy. Rank: 4 cubic, 3 quadratic, 2 linear, 1 extrapolation,
-// 0 copy. Presence known at compile time (interior of full blocks).
-template <bool CUB, bool PA, bool PC, bool PD>
+// c = v(t+s), d = v(t+3s): the spline's midpoint value (CUB: 0 linear,
+// 1 cubic, 2 natural cubic); where samples are missing the order drops to
+// quadratic (one side), linear, linear extrapolation or copy. Rank: 4 cubic,
+// 3 quadratic, 2 linear, 1 extrapolation, 0 copy. Presence known at compile
+// time (interior of full blocks).
+template <int CUB, bool PA, bool PC, bool PD>
 __device__ __forceinline__ float stencil_ct(float a, float b, float c, float d, int &rank)
 {
     if constexpr (CUB && PA && PC && PD) {
         rank = 4;
-        return ((b + c) * 9.0f - (a + d)) * 0.0625f;
+        return mid4<CUB>(a, b, c, d);
     } else if constexpr (CUB && !PA && PC && PD) {
         rank = 3;
         return ((b * 3.0f + c * 6.0f) - d) * 0.125f;
@@ -90,7 +102,7 @@ __device__ __forceinline__ float stencil_ct(float a, float b, float c, float d, 
 // The same stencil with presence known only at run time, evaluated without
 // branches (every candidate is formed, the applicable one selected; samples
 // that are missing are never selected).
-template <bool CUB>
+template <int CUB>
 __device__ __forceinline__ float stencil_rt(float a, float b, float c, float d, bool pa, bool pc,
                                             bool pd, int &rank)
 {
@@ -99,7 +111,7 @@ __device__ __forceinline__ float stencil_rt(float a, float b, float c, float d, 
     float v = pc ? vl : (pa ? ve : b);
     int r = pc ? 2 : (pa ? 1 : 0);
     if constexpr (CUB) {
-        const float vc = ((b + c) * 9.0f - (a + d)) * 0.0625f;
+        const float vc = mid4<CUB>(a, b, c, d);
         const float vqr = ((b * 3.0f + c * 6.0f) - d) * 0.125f;
         const float vql = ((b * 6.0f + c * 3.0f) - a) * 0.125f;
         const bool full = pa && pc && pd, right = !pa && pc && pd, left = pa && pc && !pd;
@@ -183,14 +195,14 @@ __device__ __forceinline__ CrossSamples cross_load(const float *__restrict__ v, 
 }
 // 1-D stencil across the line direction from its samples (missing samples
 // are never selected).
-template <bool CUB, bool FULL>
+template <int CUB, bool FULL>
 __device__ __forceinline__ float cross_eval(const CrossSamples &s, const CrossFlags &f, int &rank)
 {
     if constexpr (FULL) {
         // inside a full block a target always has its +s neighbour
         const float vl = (s.b + s.c) * 0.5f;
         if constexpr (CUB) {
-            const float vc = ((s.b + s.c) * 9.0f - (s.a + s.d)) * 0.0625f;
+            const float vc = mid4<CUB>(s.a, s.b, s.c, s.d);
             const float vqr = ((s.b * 3.0f + s.c * 6.0f) - s.d) * 0.125f;
             const float vql = ((s.b * 6.0f + s.c * 3.0f) - s.a) * 0.125f;
             const float v1 = f.pa ? vql : vl;
@@ -215,7 +227,7 @@ __device__ __forceinline__ float cross_eval(const CrossSamples &s, const CrossFl
 // x, y, z order is odd and used). nA: extent of the block along A (17 for
 // full blocks). The stride is a run-time value so that one compact code path
 // serves every level.
-template <int TZ, int A, int MB, int MC, bool CUB, bool COMP, bool FULL, int BS>
+template <int TZ, int A, int MB, int MC, int CUB, bool COMP, bool FULL, int BS>
 __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restrict__ cb,
                                         const uint8_t *__restrict__ cl, const Geo &g, int x0,
                                         int y0, int z0, int nA, int S, const QParams &q)
@@ -286,7 +298,7 @@ __device__ __forceinline__ void do_line(float *__restrict__ v, uint8_t *__restri
         float pA;
         if (CUB && pa && pc && pd) {
             rA = 4;
-            pA = ((b + c) * 9.0f - (a + d)) * 0.0625f;
+            pA = mid4<CUB>(a, b, c, d);
         } else {
             pA = stencil_rt<CUB>(a, b, c, d, pa, pc, pd, rA);
         }
@@ -410,7 +422,7 @@ __device__ __forceinline__ LineGroup make_group(int kind, int A, int modeB, int 
 // kinds: 0..2 plain lines along z, y, x; 3 along x with y odd (MD xy);
 // 4 along z with x odd (MD xz); 5 along z with y odd (MD yz); 6 along z with x
 // and y odd (MD xyz).
-template <int TZ, bool CUB, bool COMP, bool FULL, int BS>
+template <int TZ, int CUB, bool COMP, bool FULL, int BS>
 __device__ __forceinline__ void run_line(const LineGroup &G, int l, int S, float *v, uint8_t *cb,
                                          const uint8_t *cl, const Geo &g, const QParams &q)
 {
@@ -449,7 +461,7 @@ __device__ __forceinline__ void run_line(const LineGroup &G, int l, int S, float
 // start and the eight targets run unrolled; only the cross-axis sample
 // presence (fixed per line) is a run-time choice. Arithmetic is the same as
 // in do_line, operation for operation.
-template <int TZ, int A, int MB, int MC, bool CUB, bool COMP>
+template <int TZ, int A, int MB, int MC, int CUB, bool COMP>
 __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__restrict__ cb,
                                            const uint8_t *__restrict__ cl, const Geo &g, int x0,
                                            int y0, int z0, const QParams &q)
@@ -550,7 +562,7 @@ __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__res
     });
 }
 
-template <int TZ, bool CUB, bool COMP>
+template <int TZ, int CUB, bool COMP>
 __device__ __forceinline__ void run_line_s1(const LineGroup &G, int l, float *v, uint8_t *cb,
                                             const uint8_t *cl, const Geo &g, const QParams &q)
 {
@@ -584,7 +596,7 @@ __device__ __forceinline__ void run_line_s1(const LineGroup &G, int l, float *v,
 // the j-th axis of the order every target whose last odd axis (in that order)
 // is that axis; axes earlier in the order take every multiple of S, later
 // ones even multiples only.
-template <int TZ, bool CUB, bool COMP, bool FULL, int BS>
+template <int TZ, int CUB, bool COMP, bool FULL, int BS>
 __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g,
                                             int S, bool md, int perm, const QParams &q)
 {
@@ -663,20 +675,25 @@ template <int TZ, bool COMP, int BS = 16>
 __device__ __forceinline__ void level(float *v, uint8_t *cb, const uint8_t *cl, const Geo &g, int S,
                                       const uint8_t *cfg, const QParams &q)
 {
-    const bool cub = cfg[0] != 0;
+    const int spline = cfg[0];
     const bool md = cfg[1] == 0;
     const int perm = cfg[2];
     const bool full = g.ex == BS + 1 && g.ey == BS + 1 && g.ez == BS * TZ + 1;
-    if (cub) {
+    if (spline == 2) {
         if (full)
-            level_lines<TZ, true, COMP, true, BS>(v, cb, cl, g, S, md, perm, q);
+            level_lines<TZ, 2, COMP, true, BS>(v, cb, cl, g, S, md, perm, q);
         else
-            level_lines<TZ, true, COMP, false, BS>(v, cb, cl, g, S, md, perm, q);
+            level_lines<TZ, 2, COMP, false, BS>(v, cb, cl, g, S, md, perm, q);
+    } else if (spline == 1) {
+        if (full)
+            level_lines<TZ, 1, COMP, true, BS>(v, cb, cl, g, S, md, perm, q);
+        else
+            level_lines<TZ, 1, COMP, false, BS>(v, cb, cl, g, S, md, perm, q);
     } else {
         if (full)
-            level_lines<TZ, false, COMP, true, BS>(v, cb, cl, g, S, md, perm, q);
+            level_lines<TZ, 0, COMP, true, BS>(v, cb, cl, g, S, md, perm, q);
         else
-            level_lines<TZ, false, COMP, false, BS>(v, cb, cl, g, S, md, perm, q);
+            level_lines<TZ, 0, COMP, false, BS>(v, cb, cl, g, S, md, perm, q);
     }
 }
 

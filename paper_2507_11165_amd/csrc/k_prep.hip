@@ -33,6 +33,12 @@ __global__ __launch_bounds__(256) void k_init_compress(const Job *__restrict__ j
         J.lb_a[i] = 0;
         J.lb_b[i] = 0;
     }
+    // look-back words of the last stages' chunks and of the outlier units
+    for (uint64_t i = blockIdx.x * 256ull + t; i < J.n_lc; i += 256ull * gridDim.x)
+        J.lb_c[i] = 0;
+    const uint64_t nd = J.n_ou > J.n_lc ? J.n_ou : J.n_lc;
+    for (uint64_t i = blockIdx.x * 256ull + t; i < nd; i += 256ull * gridDim.x)
+        J.lb_d[i] = 0;
 }
 
 void launch_init_compress(const Job *d_jobs, int njobs, uint64_t max_chunks, Counters *cnt,
@@ -173,8 +179,8 @@ void launch_eps(const Job *d_jobs, int njobs, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 // Tuner (Sec. 5.1.3). Full 17^3 blocks with 0.2 % of the volume are sampled at
-// even spacing. Every level is tested with the 14 candidates {LIN, CUB} x
-// {MD, SEQ over the 6 dimension orders}, predicting from ORIGINAL values; the
+// even spacing. Every level is tested with the 21 candidates {LIN, CUB, NAT}
+// x {MD, SEQ over the 6 dimension orders}, predicting from ORIGINAL values; the
 // candidate with the smallest aggregated |x - p| wins per level (ties: lower
 // index). Each |x - p| is counted in units of 2*eps/65536, rounded and capped
 // at 2^36, and summed as a 64-bit integer, so the totals are exact and do not
@@ -183,7 +189,7 @@ void launch_eps(const Job *d_jobs, int njobs, hipStream_t s)
 // Work balance follows the paper's idea of giving the expensive fine levels
 // more thread blocks: per sample, one block tests strides 8 and 4, two
 // blocks share stride 2 and six share stride 1. Unlike the paper, each block
-// tests all 14 candidates on its share of targets, because the candidates
+// tests all 21 candidates on its share of targets, because the candidates
 // reuse the same per-axis stencils.
 // ---------------------------------------------------------------------------
 constexpr int kTuneParts = 9;
@@ -191,12 +197,17 @@ constexpr int kTuneParts = 9;
 __constant__ int8_t c_perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
 // 1-D spline stencil (Sec. 5.1.2): Lagrange weights at the midpoint from the
-// samples at -3s, -s, +s, +3s; lower orders where samples are missing.
+// samples at -3s, -s, +s, +3s; lower orders where samples are missing. With
+// all four samples, spline 2 is the natural cubic spline through them (zero
+// second derivative at the outer samples): weights (-3, 23, 23, -3) / 40.
 __device__ __forceinline__ float stencil_1d(float a, float b, float c, float d, bool pa, bool pc,
-                                            bool pd, bool cub, int &rank)
+                                            bool pd, int spline, int &rank)
 {
+    const bool cub = spline != 0;
     if (cub && pa && pc && pd) {
         rank = 4;
+        if (spline == 2)
+            return ((b + c) * 23.0f - (a + d) * 3.0f) / 40.0f;
         return ((b + c) * 9.0f - (a + d)) * 0.0625f;
     }
     if (cub && pc && pd) {
@@ -257,37 +268,41 @@ __device__ inline uint64_t wave_sum_u64(uint64_t v)
     return v;
 }
 
-// Accumulate the 14 candidate error sums of the targets [g0, g1) of the
-// stride-s grid of a block held in LDS (side 17).
-__device__ void tune_level(const float *__restrict__ blk, int s, int g0, int g1, double scale,
-                           uint64_t acc[kCands])
+// Accumulate the 21 candidate error sums of the targets [g0, g1) of the
+// stride-s grid of a block held in LDS (strides 17*17, 17, 1) whose extent on
+// axis k is E[k] (17, or 1 on a flat axis).
+__device__ void tune_level(const float *__restrict__ blk, const int E[3], int s, int g0, int g1,
+                           double scale, uint64_t acc[kCands])
 {
-    const int G = 16 / s + 1;
+    const int Gx = E[0] == 1 ? 1 : 16 / s + 1, Gy = E[1] == 1 ? 1 : 16 / s + 1,
+              Gz = E[2] == 1 ? 1 : 16 / s + 1;
     for (int g = g0 + (int)threadIdx.x; g < g1; g += blockDim.x) {
-        int iz = g % G, r = g / G, iy = r % G, ix = r / G;
+        int iz = g % Gz, r = g / Gz, iy = r % Gy, ix = r / Gy;
         int mask = (ix & 1) | ((iy & 1) << 1) | ((iz & 1) << 2);
         if (mask == 0)
             continue;
         int t[3] = {ix * s, iy * s, iz * s};
         const int st[3] = {kSide * kSide, kSide, 1};
         int li = (t[0] * kSide + t[1]) * kSide + t[2];
-        float pl[3] = {0, 0, 0}, pc3[3] = {0, 0, 0};
-        int rl[3] = {-1, -1, -1}, rc[3] = {-1, -1, -1};
+        float pl[3] = {0, 0, 0}, pc3[3] = {0, 0, 0}, pn[3] = {0, 0, 0};
+        int rl[3] = {-1, -1, -1}, rc[3] = {-1, -1, -1}, rn[3] = {-1, -1, -1};
         for (int k = 0; k < 3; k++) {
             if (!((mask >> k) & 1))
                 continue;
             int tk = t[k];
-            bool pa = tk - 3 * s >= 0, pcp = tk + s <= kSide - 1, pd = tk + 3 * s <= kSide - 1;
+            bool pa = tk - 3 * s >= 0, pcp = tk + s <= E[k] - 1, pd = tk + 3 * s <= E[k] - 1;
             float b = blk[li - s * st[k]];
             float a = pa ? blk[li - 3 * s * st[k]] : 0.0f;
             float c = pcp ? blk[li + s * st[k]] : 0.0f;
             float d = pd ? blk[li + 3 * s * st[k]] : 0.0f;
-            pl[k] = stencil_1d(a, b, c, d, pa, pcp, pd, false, rl[k]);
-            pc3[k] = stencil_1d(a, b, c, d, pa, pcp, pd, true, rc[k]);
+            pl[k] = stencil_1d(a, b, c, d, pa, pcp, pd, 0, rl[k]);
+            pc3[k] = stencil_1d(a, b, c, d, pa, pcp, pd, 1, rc[k]);
+            pn[k] = stencil_1d(a, b, c, d, pa, pcp, pd, 2, rn[k]);
         }
         float x = blk[li];
         acc[0] += tune_term(x, md_combine(pl, rl, mask), scale);
         acc[7] += tune_term(x, md_combine(pc3, rc, mask), scale);
+        acc[14] += tune_term(x, md_combine(pn, rn, mask), scale);
         for (int perm = 0; perm < 6; perm++) {
             int axis = -1;
             for (int j = 0; j < 3; j++)
@@ -295,8 +310,10 @@ __device__ void tune_level(const float *__restrict__ blk, int s, int g0, int g1,
                     axis = c_perm[perm][j];
             float vl = axis == 0 ? pl[0] : (axis == 1 ? pl[1] : pl[2]);
             float vc = axis == 0 ? pc3[0] : (axis == 1 ? pc3[1] : pc3[2]);
+            float vn = axis == 0 ? pn[0] : (axis == 1 ? pn[1] : pn[2]);
             acc[1 + perm] += tune_term(x, vl, scale);
             acc[8 + perm] += tune_term(x, vc, scale);
+            acc[15 + perm] += tune_term(x, vn, scale);
         }
     }
 }
@@ -342,28 +359,36 @@ __global__ __launch_bounds__(256) void k_tune(const Job *__restrict__ jobs, int 
     const uint64_t bc = idx % J.n_full[2], bb = (idx / J.n_full[2]) % J.n_full[1],
                    ba = idx / ((uint64_t)J.n_full[1] * J.n_full[2]);
     const uint64_t dy = J.dims[1], dz = J.dims[2];
+    // a full block spans 17 points per axis, 1 on a flat axis (2-D / 1-D fields)
+    const int E[3] = {J.dims[0] == 1 ? 1 : kSide, J.dims[1] == 1 ? 1 : kSide,
+                      J.dims[2] == 1 ? 1 : kSide};
     for (int i = threadIdx.x; i < kSide * kSide * kSide; i += blockDim.x) {
         int z = i % kSide, r = i / kSide, y = r % kSide, x = r / kSide;
-        blk[i] = gmem(J.field)[((ba * kAnchor + x) * dy + (bb * kAnchor + y)) * dz +
-                               bc * kAnchor + z];
+        if (x < E[0] && y < E[1] && z < E[2])
+            blk[i] = gmem(J.field)[((ba * kAnchor + x) * dy + (bb * kAnchor + y)) * dz +
+                                   bc * kAnchor + z];
     }
     __syncthreads();
+    auto targets = [&](int s) {
+        const int g = 16 / s + 1;
+        return (E[0] == 1 ? 1 : g) * (E[1] == 1 ? 1 : g) * (E[2] == 1 ? 1 : g);
+    };
     const double scale = st->tune_scale;
     uint64_t acc[kCands];
     for (int c = 0; c < kCands; c++)
         acc[c] = 0;
     if (part == 0) {
-        tune_level(blk, 8, 0, 27, scale, acc);
+        tune_level(blk, E, 8, 0, targets(8), scale, acc);
         tune_flush(st, 0, acc, red);
-        tune_level(blk, 4, 0, 125, scale, acc);
+        tune_level(blk, E, 4, 0, targets(4), scale, acc);
         tune_flush(st, 1, acc, red);
     } else if (part <= 2) {
-        const int G3 = 9 * 9 * 9, h = part - 1;
-        tune_level(blk, 2, h * G3 / 2, (h + 1) * G3 / 2, scale, acc);
+        const int G3 = targets(2), h = part - 1;
+        tune_level(blk, E, 2, h * G3 / 2, (h + 1) * G3 / 2, scale, acc);
         tune_flush(st, 2, acc, red);
     } else {
-        const int G3 = kSide * kSide * kSide, h = part - 3;
-        tune_level(blk, 1, h * G3 / 6, (h + 1) * G3 / 6, scale, acc);
+        const int G3 = targets(1), h = part - 3;
+        tune_level(blk, E, 1, h * G3 / 6, (h + 1) * G3 / 6, scale, acc);
         tune_flush(st, 3, acc, red);
     }
 }

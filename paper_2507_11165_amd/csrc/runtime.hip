@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -337,6 +338,7 @@ struct Parsed {
     uint64_t N;
     int idx_bytes;
     uint64_t off_anchors, off_oidx, off_oval, off_payload;
+    uint64_t off_lcsizes, n_lc; // last stages: chunk-size table and chunk count
     float const_value;
 };
 
@@ -358,8 +360,10 @@ hiz_status parse_header(std::string *msg, const uint8_t *h, uint64_t n, uint64_t
         BAD("bad magic or version");
     I.mode = h[H_MODE];
     const uint8_t flags = h[H_FLAGS];
-    if (I.mode > 1 || (flags & ~3))
-        BAD("bad mode or flags");
+    I.pipeline = h[H_PIPE];
+    I.reorder = (flags & kFlagReorder) ? 1 : 0;
+    if (I.mode > 1 || (flags & ~7) || I.pipeline > PIPE_CR)
+        BAD("bad mode, flags or pipeline");
     uint64_t N = 1;
     for (int k = 0; k < 3; k++) {
         I.dims[k] = get_le<uint64_t>(h + H_DIMS + 8 * k);
@@ -377,6 +381,8 @@ hiz_status parse_header(std::string *msg, const uint8_t *h, uint64_t n, uint64_t
     I.total_bytes = get_le<uint64_t>(h + H_TOTAL);
     if (flags & kFlagConst) {
         I.constant = 1;
+        if (I.pipeline != PIPE_HF || I.reorder)
+            BAD("bad constant stream");
         if (I.total_bytes != kHdrBytes + 4u || in_size < I.total_bytes)
             BAD("bad constant stream");
         if (n >= kHdrBytes + 4u)
@@ -388,31 +394,63 @@ hiz_status parse_header(std::string *msg, const uint8_t *h, uint64_t n, uint64_t
     for (int l = 0; l < kLevels; l++) {
         for (int k = 0; k < 3; k++)
             I.level_cfg[l][k] = h[H_CFG + 3 * l + k];
-        if (I.level_cfg[l][0] > 1 || I.level_cfg[l][1] > 1 || I.level_cfg[l][2] > 5)
+        if (I.level_cfg[l][0] > 2 || I.level_cfg[l][1] > 1 || I.level_cfg[l][2] > 5)
             BAD("bad level configuration");
     }
     I.chunk = get_le<uint32_t>(h + H_CHUNK);
-    if (I.chunk < 256 || I.chunk > 65536 || (I.chunk & (I.chunk - 1)))
-        BAD("bad chunk length");
     I.n_outliers = get_le<uint64_t>(h + H_NOUT);
     I.payload_words = get_le<uint64_t>(h + H_PWORDS);
     I.n_chunks = get_le<uint64_t>(h + H_NCHUNKS);
+    I.lc_bytes = get_le<uint64_t>(h + H_LCBYTES);
+    P->n_lc = get_le<uint64_t>(h + H_NLC);
     const uint64_t n_anchors = get_le<uint64_t>(h + H_NANCH);
+    if (I.pipeline == PIPE_TP) {
+        // no Huffman stage: the stages run on the N code bytes
+        if (I.chunk != 0 || I.n_chunks != 0 || I.payload_words != 0)
+            BAD("bad throughput-mode header");
+        if (P->n_lc != cdiv(N, kLcChunk) || I.lc_bytes > N)
+            BAD("bad stage section size");
+    } else {
+        if (I.chunk < 256 || I.chunk > 65536 || (I.chunk & (I.chunk - 1)))
+            BAD("bad chunk length");
+        if (I.n_chunks != cdiv(N, I.chunk))
+            BAD("bad chunk count");
+        if (I.payload_words > N + I.n_chunks)
+            BAD("bad payload size");
+        if (I.pipeline == PIPE_HF && (P->n_lc != 0 || I.lc_bytes != 0))
+            BAD("bad stage section size");
+        if (I.pipeline == PIPE_CR &&
+            (P->n_lc != cdiv(4 * I.payload_words, kLcChunk) || I.lc_bytes > 4 * I.payload_words))
+            BAD("bad stage section size");
+    }
     P->idx_bytes = N < (1ull << 32) ? 4 : 8;
     if (((flags & kFlagIdx64) != 0) != (P->idx_bytes == 8))
         BAD("bad index width flag");
-    if (I.n_chunks != cdiv(N, I.chunk))
-        BAD("bad chunk count");
     if (n_anchors != cdiv(I.dims[0], kAnchor) * cdiv(I.dims[1], kAnchor) * cdiv(I.dims[2], kAnchor))
         BAD("bad anchor count");
-    if (I.n_outliers > N || I.payload_words > N + I.n_chunks)
-        BAD("bad outlier or payload size");
-    P->off_anchors = align16(kOffChunks + 4 * I.n_chunks);
+    if (I.n_outliers > N)
+        BAD("bad outlier count");
+    // sections: HF payload last; TP stage sizes at 384, stage data last; CR
+    // Huffman word counts at 384, stage sizes and data after the outliers
+    const uint64_t table = I.pipeline == PIPE_TP ? P->n_lc : I.n_chunks;
+    P->off_anchors = align16(kOffChunks + 4 * table);
     P->off_oidx = align16(P->off_anchors + 4 * n_anchors);
     P->off_oval = align16(P->off_oidx + (uint64_t)P->idx_bytes * I.n_outliers);
-    P->off_payload = align16(P->off_oval + 4 * I.n_outliers);
-    if (I.total_bytes != P->off_payload + 4 * I.payload_words || I.total_bytes > in_size)
+    const uint64_t end_oval = P->off_oval + 4 * I.n_outliers;
+    uint64_t total;
+    if (I.pipeline == PIPE_HF) {
+        P->off_payload = align16(end_oval);
+        total = P->off_payload + 4 * I.payload_words;
+    } else {
+        P->off_lcsizes = I.pipeline == PIPE_TP ? (uint64_t)kOffChunks : align16(end_oval);
+        P->off_payload = I.pipeline == PIPE_TP ? align16(end_oval)
+                                               : align16(P->off_lcsizes + 4 * P->n_lc);
+        total = P->off_payload + I.lc_bytes;
+    }
+    if (I.total_bytes != total || I.total_bytes > in_size)
         BAD("stream size does not match its header");
+    if (I.pipeline == PIPE_TP)
+        return HIZ_OK;
     if (n >= (uint64_t)kOffChunks) {
         // the code lengths must form a complete prefix code (one symbol: length 1)
         const uint8_t *len = h + kOffLen;
@@ -436,28 +474,54 @@ hiz_status parse_header(std::string *msg, const uint8_t *h, uint64_t n, uint64_t
 bool valid_cfg(const uint8_t cfg[4][3])
 {
     for (int l = 0; l < 4; l++)
-        if (cfg[l][0] > 1 || cfg[l][1] > 1 || cfg[l][2] > 5)
+        if (cfg[l][0] > 2 || cfg[l][1] > 1 || cfg[l][2] > 5)
             return false;
     return true;
 }
 
-// Shared parameters of a call (NULL = defaults) and its tile shape.
-hiz_status resolve_params(hiz_ctx *c, const hiz_params *params, hiz_params &p, int &tz)
+// Shared parameters of a call (NULL = defaults) and its tile shape; on a
+// failure `msg` names the bad parameter.
+hiz_status check_params(const hiz_params *params, hiz_params &p, int &tz, const char *&msg)
 {
     memset(&p, 0, sizeof(p));
     p.tune = 1;
     for (int l = 0; l < 4; l++)
         p.level_cfg[l][0] = HIZ_SPLINE_CUBIC;
+    p.reorder = -1;
     if (params)
         p = *params;
-    if (!valid_cfg(p.level_cfg))
-        return fail(c, HIZ_ERR_ARG, "bad level configuration");
-    if (p.chunk && (p.chunk < 256 || p.chunk > 65536 || (p.chunk & (p.chunk - 1))))
-        return fail(c, HIZ_ERR_ARG, "chunk must be a power of two in [256, 65536]");
+    msg = "";
+    if (!valid_cfg(p.level_cfg)) {
+        msg = "bad level configuration";
+        return HIZ_ERR_ARG;
+    }
+    if (p.chunk && (p.chunk < 256 || p.chunk > 65536 || (p.chunk & (p.chunk - 1)))) {
+        msg = "chunk must be a power of two in [256, 65536]";
+        return HIZ_ERR_ARG;
+    }
     tz = p.tile_z ? (int)p.tile_z : kDefaultTileZ;
-    if (tz != 1 && tz != 2 && tz != 4)
-        return fail(c, HIZ_ERR_ARG, "tile_z must be 1, 2 or 4");
+    if (tz != 1 && tz != 2 && tz != 4) {
+        msg = "tile_z must be 1, 2 or 4";
+        return HIZ_ERR_ARG;
+    }
+    if (p.pipeline > HIZ_PIPE_CR) {
+        msg = "pipeline must be HIZ_PIPE_HUFFMAN, HIZ_PIPE_TP or HIZ_PIPE_CR";
+        return HIZ_ERR_ARG;
+    }
+    if (p.reorder < -1 || p.reorder > 1) {
+        msg = "reorder must be -1, 0 or 1";
+        return HIZ_ERR_ARG;
+    }
+    if (p.reorder < 0)
+        p.reorder = p.pipeline == HIZ_PIPE_CR ? 1 : 0;
     return HIZ_OK;
+}
+
+hiz_status resolve_params(hiz_ctx *c, const hiz_params *params, hiz_params &p, int &tz)
+{
+    const char *msg = "";
+    hiz_status rc = check_params(params, p, tz, msg);
+    return rc ? fail(c, rc, "%s", msg) : HIZ_OK;
 }
 
 // Tiles whose owned points all lie inside the field (their coarse levels run
@@ -476,7 +540,7 @@ uint64_t full_tiles(const Job &J) { return (uint64_t)J.nf[0] * J.nf[1] * J.nf[2]
 // filled in by the caller once the workspace is laid out.
 hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode, double eb,
                          const hiz_params &p, int tz, void *d_out, uint64_t out_cap, Job &J,
-                         std::string &msg)
+                         const char *&msg)
 {
     if (!d_field || !dims || !d_out) {
         msg = "NULL argument";
@@ -510,7 +574,10 @@ hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode,
     for (int k = 0; k < 3; k++) {
         J.dims[k] = dims[k];
         J.nb[k] = (uint32_t)cdiv(dims[k], kAnchor);
-        J.n_full[k] = dims[k] >= (uint64_t)kSide ? (uint32_t)((dims[k] - kSide) / kAnchor + 1) : 0;
+        // full blocks per axis: 17 points, or the single point of a flat axis
+        J.n_full[k] = dims[k] == 1 ? 1
+                      : dims[k] >= (uint64_t)kSide ? (uint32_t)((dims[k] - kSide) / kAnchor + 1)
+                                                   : 0;
     }
     J.N = N;
     J.ntz = (uint32_t)cdiv(J.nb[2], tz);
@@ -528,13 +595,35 @@ hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode,
     const uint64_t n_full = (uint64_t)J.n_full[0] * J.n_full[1] * J.n_full[2];
     if (J.tune && n_full > 0) {
         // Sec. 5.1.3: about 0.2 % of the points, in whole full blocks
-        uint64_t ns = std::max<uint64_t>(1, cdiv(2 * N, 1000ull * 4913ull));
+        uint64_t vol = 1;
+        for (int k = 0; k < 3; k++)
+            vol *= dims[k] == 1 ? 1 : (uint64_t)kSide;
+        uint64_t ns = std::max<uint64_t>(1, cdiv(2 * N, 1000ull * vol));
         J.n_samples = (uint32_t)std::min<uint64_t>(ns, n_full);
     }
     J.n_tune = (uint64_t)J.n_samples * 9;
     J.n_tiles = (uint64_t)J.nb[0] * J.nb[1] * J.ntz;
     J.n_groups = cdiv(J.n_chunks, kEncGroupChunks);
     set_full_tiles(J, tz);
+    J.pipe = (uint8_t)p.pipeline;
+    J.reorder = (uint8_t)(p.reorder ? 1 : 0);
+    if (J.pipe == PIPE_TP) {
+        // no Huffman stage; the stage chunk sizes take the table at 384
+        J.chunk = 0;
+        J.log2_chunk = 0;
+        J.n_chunks = 0;
+        J.n_groups = 0;
+        J.n_lc = cdiv(N, kLcChunk);
+        J.off_anchors = align16(kOffChunks + 4 * J.n_lc);
+    } else if (J.pipe == PIPE_CR) {
+        // the payload (at most one 32-bit word per code plus a padding word
+        // per chunk) waits in the workspace for the last stages
+        J.hpay_cap = 4 * (N + J.n_chunks);
+        J.n_lc = cdiv(J.hpay_cap, kLcChunk);
+    }
+    // outliers in row-major order need their own pass when the lossless stage
+    // sees the codes reordered
+    J.n_ou = J.reorder ? cdiv(N, kLcChunk) : 0;
     return HIZ_OK;
 }
 
@@ -570,12 +659,24 @@ void plan_decompress(const Parsed &P, const void *d_in, uint64_t in_size, float 
     J.n_out = P.info.n_outliers;
     J.payload_words = P.info.payload_words;
     J.eps = P.info.eps;
+    J.pipe = (uint8_t)P.info.pipeline;
+    J.reorder = (uint8_t)P.info.reorder;
+    J.n_lc = P.n_lc;
+    J.off_lcsizes = P.off_lcsizes;
+    J.off_lcdata = P.off_payload;
+    J.lc_bytes = P.info.lc_bytes;
+    if (J.pipe == PIPE_CR)
+        J.hpay_cap = 4 * J.payload_words;
 }
 
 // Totals of one enqueued sequence (also the graph key's payload).
 struct Totals {
     uint64_t mm = 0, tune = 0, tiles = 0, chunks = 0, groups = 0, dblk = 0, out = 0;
     uint64_t max_groups = 0, max_dblk = 0;
+    uint64_t lc = 0, ou = 0;   // stage chunks, outlier units
+    uint64_t max_n = 0;        // largest field (reordering launch)
+    bool reorder = false;      // some field's codes are reordered
+    uint64_t max_clear = 0;    // longest look-back array any field clears at the start
 };
 
 // Lay out the workspace for `jobs`, set their prefixes and device pointers,
@@ -586,7 +687,93 @@ struct Layout {
     Counters *d_cnt;
     uint8_t *d_res;
     uint8_t *h_res;
+    const void *h_jobs; // host copy of the Job table the sequence uploads
 };
+
+// Workspace sections of one field (offsets from the workspace base).
+struct Sections {
+    uint64_t st, codes, crec, ccode, dt, lba, lbb, woff, zoff, mm, seq, hpay, lbc, lbd;
+};
+
+// Take one field's sections from the arena and add its work units to the
+// launch totals (its work-list prefixes are the totals before it).
+void take_sections(Arena &A, Job &J, bool decompress, int tz, Totals &T, Sections &o)
+{
+    memset(&o, 0, sizeof(o));
+    o.st = A.take(sizeof(FieldState));
+    o.codes = A.take(J.N);
+    // the code sequence of the lossless stage, the ratio mode's payload, and
+    // the look-back words of the stage chunks and outlier units
+    o.seq = J.reorder ? A.take(J.N) : 0;
+    o.hpay = J.pipe == PIPE_CR ? A.take(J.hpay_cap) : 0;
+    o.lbc = A.take(8 * J.n_lc);
+    o.lbd = A.take(8 * std::max(J.n_lc, J.n_ou));
+    J.lc_begin = T.lc;
+    J.ou_begin = T.ou;
+    T.lc += J.n_lc;
+    T.ou += J.n_ou;
+    T.max_n = std::max(T.max_n, J.N);
+    T.reorder = T.reorder || J.reorder;
+    T.max_clear = std::max(T.max_clear, std::max(J.n_lc, J.n_ou));
+    o.crec = A.take(4 * coarse_values_per_tile(tz) * full_tiles(J));
+    o.ccode = decompress ? 0 : A.take(coarse_codes_per_tile(tz) * full_tiles(J));
+    if (decompress) {
+        o.dt = A.take(sizeof(DecTables));
+        o.lba = A.take(8 * J.n_dblk);
+        J.tile_begin = T.tiles;
+        J.dblk_begin = T.dblk;
+        J.out_begin = T.out;
+        T.tiles += J.n_tiles;
+        T.dblk += J.n_dblk;
+        T.out += J.n_out;
+        T.max_dblk = std::max(T.max_dblk, J.n_dblk);
+    } else {
+        o.lba = A.take(8 * J.n_groups);
+        o.lbb = A.take(8 * J.n_groups);
+        o.woff = A.take(8 * J.n_chunks);
+        o.zoff = A.take(8 * J.n_chunks);
+        o.mm = A.take(8 * std::max<uint64_t>(J.n_mm, J.n_tiles));
+        J.mm_begin = T.mm;
+        J.tune_begin = T.tune;
+        J.tile_begin = T.tiles;
+        J.chunk_begin = T.chunks;
+        J.group_begin = T.groups;
+        T.mm += J.n_mm;
+        T.tune += J.n_tune;
+        T.tiles += J.n_tiles;
+        T.chunks += J.n_chunks;
+        T.groups += J.n_groups;
+        T.max_groups = std::max(T.max_groups, J.n_groups);
+    }
+}
+
+// Device pointers of one field's sections in the workspace at `ws`.
+void bind_sections(uint8_t *ws, Job &J, bool decompress, const Sections &o)
+{
+    J.st = reinterpret_cast<FieldState *>(ws + o.st);
+    J.codes = ws + o.codes;
+    J.seq = J.reorder ? ws + o.seq : J.codes;
+    J.hpay = J.pipe == PIPE_CR ? ws + o.hpay : nullptr;
+    J.lb_c = reinterpret_cast<uint64_t *>(ws + o.lbc);
+    J.lb_d = reinterpret_cast<uint64_t *>(ws + o.lbd);
+    J.crec = reinterpret_cast<float *>(ws + o.crec);
+    J.ccode = decompress ? nullptr : ws + o.ccode;
+    J.lb_a = reinterpret_cast<uint64_t *>(ws + o.lba);
+    if (decompress) {
+        J.dt = reinterpret_cast<DecTables *>(ws + o.dt);
+    } else {
+        J.lb_b = reinterpret_cast<uint64_t *>(ws + o.lbb);
+        J.woff = reinterpret_cast<uint64_t *>(ws + o.woff);
+        J.zoff = reinterpret_cast<uint64_t *>(ws + o.zoff);
+        J.mm_part = reinterpret_cast<uint2 *>(ws + o.mm);
+    }
+}
+
+bool totals_fit(const Totals &T)
+{
+    return T.groups <= 0xffffffffull && T.dblk <= 0xffffffffull && T.tune <= 0xffffffffull &&
+           T.tiles <= 0xffffffffull && T.lc <= 0xffffffffull && T.ou <= 0xffffffffull;
+}
 
 hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, int tz, Totals &T,
                   Layout &L)
@@ -596,47 +783,11 @@ hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, int tz, T
     const uint64_t o_jobs = A.take(sizeof(Job) * nj);
     const uint64_t o_cnt = A.take(sizeof(Counters));
     const uint64_t o_res = A.take((uint64_t)kResultBytes * nj);
-    std::vector<uint64_t> o_st(nj), o_dt(nj), o_codes(nj), o_lba(nj), o_lbb(nj), o_woff(nj),
-        o_zoff(nj), o_mm(nj), o_crec(nj), o_ccode(nj);
-    const uint64_t cvals = coarse_values_per_tile(tz), ccodes = coarse_codes_per_tile(tz);
+    std::vector<Sections> o(nj);
     T = Totals();
-    for (int j = 0; j < nj; j++) {
-        Job &J = jobs[j];
-        o_st[j] = A.take(sizeof(FieldState));
-        o_codes[j] = A.take(J.N);
-        o_crec[j] = A.take(4 * cvals * full_tiles(J));
-        o_ccode[j] = decompress ? 0 : A.take(ccodes * full_tiles(J));
-        if (decompress) {
-            o_dt[j] = A.take(sizeof(DecTables));
-            o_lba[j] = A.take(8 * J.n_dblk);
-            J.tile_begin = T.tiles;
-            J.dblk_begin = T.dblk;
-            J.out_begin = T.out;
-            T.tiles += J.n_tiles;
-            T.dblk += J.n_dblk;
-            T.out += J.n_out;
-            T.max_dblk = std::max(T.max_dblk, J.n_dblk);
-        } else {
-            o_lba[j] = A.take(8 * J.n_groups);
-            o_lbb[j] = A.take(8 * J.n_groups);
-            o_woff[j] = A.take(8 * J.n_chunks);
-            o_zoff[j] = A.take(8 * J.n_chunks);
-            o_mm[j] = A.take(8 * std::max<uint64_t>(J.n_mm, J.n_tiles));
-            J.mm_begin = T.mm;
-            J.tune_begin = T.tune;
-            J.tile_begin = T.tiles;
-            J.chunk_begin = T.chunks;
-            J.group_begin = T.groups;
-            T.mm += J.n_mm;
-            T.tune += J.n_tune;
-            T.tiles += J.n_tiles;
-            T.chunks += J.n_chunks;
-            T.groups += J.n_groups;
-            T.max_groups = std::max(T.max_groups, J.n_groups);
-        }
-    }
-    if (T.groups > 0xffffffffull || T.dblk > 0xffffffffull || T.tune > 0xffffffffull ||
-        T.tiles > 0xffffffffull)
+    for (int j = 0; j < nj; j++)
+        take_sections(A, jobs[j], decompress, tz, T, o[j]);
+    if (!totals_fit(T))
         return fail(c, HIZ_ERR_ARG, "batch too large for one launch");
     hiz_status rc = ensure_ws(c, A.off);
     if (rc)
@@ -646,27 +797,14 @@ hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, int tz, T
     if (rc)
         return rc;
     uint8_t *ws = static_cast<uint8_t *>(c->ws);
-    for (int j = 0; j < nj; j++) {
-        Job &J = jobs[j];
-        J.st = reinterpret_cast<FieldState *>(ws + o_st[j]);
-        J.codes = ws + o_codes[j];
-        J.crec = reinterpret_cast<float *>(ws + o_crec[j]);
-        J.ccode = decompress ? nullptr : ws + o_ccode[j];
-        J.lb_a = reinterpret_cast<uint64_t *>(ws + o_lba[j]);
-        if (decompress) {
-            J.dt = reinterpret_cast<DecTables *>(ws + o_dt[j]);
-        } else {
-            J.lb_b = reinterpret_cast<uint64_t *>(ws + o_lbb[j]);
-            J.woff = reinterpret_cast<uint64_t *>(ws + o_woff[j]);
-            J.zoff = reinterpret_cast<uint64_t *>(ws + o_zoff[j]);
-            J.mm_part = reinterpret_cast<uint2 *>(ws + o_mm[j]);
-        }
-    }
+    for (int j = 0; j < nj; j++)
+        bind_sections(ws, jobs[j], decompress, o[j]);
     memcpy(c->pinned, jobs.data(), sizeof(Job) * nj);
     L.d_jobs = reinterpret_cast<Job *>(ws + o_jobs);
     L.d_cnt = reinterpret_cast<Counters *>(ws + o_cnt);
     L.d_res = ws + o_res;
     L.h_res = c->pinned + job_bytes;
+    L.h_jobs = c->pinned;
     return HIZ_OK;
 }
 
@@ -675,10 +813,10 @@ hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, int tz, T
 void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int tz,
                       hipStream_t s, bool prof)
 {
-    hipMemcpyAsync(L.d_jobs, c->pinned, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(L.d_jobs, L.h_jobs, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
     {
         Scope sc(c, s, "init", prof);
-        launch_init_compress(L.d_jobs, nj, T.max_groups, L.d_cnt, s);
+        launch_init_compress(L.d_jobs, nj, std::max(T.max_groups, T.max_clear), L.d_cnt, s);
     }
     if (T.mm) {
         Scope sc(c, s, "minmax", prof);
@@ -705,13 +843,25 @@ void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int 
         launch_predict(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, false), L.d_cnt,
                        s);
     }
+    if (T.reorder) {
+        Scope sc(c, s, "reorder", prof);
+        launch_reorder(L.d_jobs, nj, T.max_n, false, s);
+    }
     {
         Scope sc(c, s, "codebook", prof);
         launch_codebook(L.d_jobs, nj, s);
     }
-    {
+    if (T.chunks) {
         Scope sc(c, s, "encode", prof);
         launch_encode(L.d_jobs, nj, T.chunks, T.groups, L.d_cnt, encode_grid(c), s);
+    }
+    if (T.ou) {
+        Scope sc(c, s, "outliers", prof);
+        launch_outliers(L.d_jobs, nj, T.ou, L.d_cnt, s);
+    }
+    if (T.lc) {
+        Scope sc(c, s, "lc_encode", prof);
+        launch_lc_encode(L.d_jobs, nj, T.lc, L.d_cnt, s);
     }
     launch_gather_results(L.d_jobs, nj, L.d_res, s);
     hipMemcpyAsync(L.h_res, L.d_res, (size_t)kResultBytes * nj, hipMemcpyDeviceToHost, s);
@@ -721,18 +871,26 @@ void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int 
 void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int tz,
                         hipStream_t s, bool prof)
 {
-    hipMemcpyAsync(L.d_jobs, c->pinned, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(L.d_jobs, L.h_jobs, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
     {
         Scope sc(c, s, "init_dec", prof);
-        launch_init_decompress(L.d_jobs, nj, T.max_dblk, L.d_cnt, s);
+        launch_init_decompress(L.d_jobs, nj, std::max(T.max_dblk, T.max_clear), L.d_cnt, s);
     }
-    {
+    if (T.dblk) {
         Scope sc(c, s, "dec_tables", prof);
         launch_dec_tables(L.d_jobs, nj, s);
     }
-    {
+    if (T.lc) {
+        Scope sc(c, s, "lc_decode", prof);
+        launch_lc_decode(L.d_jobs, nj, T.lc, L.d_cnt, s);
+    }
+    if (T.dblk) {
         Scope sc(c, s, "decode", prof);
         launch_decode(L.d_jobs, nj, T.dblk, L.d_cnt, s);
+    }
+    if (T.reorder) {
+        Scope sc(c, s, "unreorder", prof);
+        launch_reorder(L.d_jobs, nj, T.max_n, true, s);
     }
     if (T.out) {
         Scope sc(c, s, "scatter", prof);
@@ -770,9 +928,9 @@ hiz_status enqueue(hiz_ctx *c, int kind, const Layout &L, int nj, const Totals &
     key.kind = kind;
     key.njobs = nj;
     key.tz = tz;
-    const uint64_t v[12] = {T.mm,  T.tune,     T.tiles,    T.chunks,
-                            T.groups, T.dblk,  T.out,      T.max_groups,
-                            T.max_dblk, (uint64_t)c->cus, 0, 0};
+    const uint64_t v[12] = {T.mm,       T.tune,  T.tiles, T.chunks,
+                            T.groups,   T.dblk,  T.out,   T.max_groups,
+                            T.max_dblk, (uint64_t)c->cus, T.lc, T.ou};
     memcpy(key.v, v, sizeof(v));
     key.ws = c->ws;
     key.pinned = c->pinned;
@@ -886,8 +1044,11 @@ hiz_status submit_compress(hiz_ctx *c, int n, const float *const *d_fields, cons
     for (int i = 0; i < n; i++) {
         Job J;
         B.cap[i] = caps[i];
+        const char *m = "";
         B.status[i] = plan_compress(d_fields[i], dims + 3 * i, modes[i], ebs[i], p, tz, d_outs[i],
-                                    caps[i], J, B.msg[i]);
+                                    caps[i], J, m);
+        if (B.status[i])
+            B.msg[i] = m;
         if (B.status[i] == HIZ_OK) {
             jobs.push_back(J);
             B.field.push_back(i);
@@ -909,9 +1070,13 @@ hiz_status submit_compress(hiz_ctx *c, int n, const float *const *d_fields, cons
     return rc ? abandon(c, s, rc) : rc;
 }
 
+// h_hdrs (may be NULL): host copies of the first kOffChunks bytes of every
+// stream (fewer when a stream is shorter), read by the caller beforehand; then
+// nothing here waits for the device.
 hiz_status submit_decompress(hiz_ctx *c, int n, const void *const *d_ins,
                              const uint64_t *in_sizes, float *const *d_fields,
-                             const uint64_t *field_caps, hipStream_t s)
+                             const uint64_t *field_caps, hipStream_t s,
+                             const uint8_t *h_hdrs = nullptr)
 {
     c->err.clear();
     if (n < 0 || n > kMaxBatch)
@@ -947,11 +1112,14 @@ hiz_status submit_decompress(hiz_ctx *c, int n, const void *const *d_ins,
             B.msg[i] = "stream shorter than its header";
             continue;
         }
-        if (hipMemcpyAsync(c->pinned + (uint64_t)kOffChunks * i, d_ins[i], nh[i],
-                           hipMemcpyDeviceToHost, s) != hipSuccess)
+        if (h_hdrs)
+            memcpy(c->pinned + (uint64_t)kOffChunks * i, h_hdrs + (uint64_t)kOffChunks * i, nh[i]);
+        else if (hipMemcpyAsync(c->pinned + (uint64_t)kOffChunks * i, d_ins[i], nh[i],
+                                hipMemcpyDeviceToHost, s) != hipSuccess)
             return abandon(c, s, fail(c, HIZ_ERR_HIP, "cannot read the header of stream %d", i));
     }
-    HIP_TRY(c, hipStreamSynchronize(s));
+    if (!h_hdrs)
+        HIP_TRY(c, hipStreamSynchronize(s));
     std::vector<Parsed> P(n);
     std::vector<Job> jobs;
     for (int i = 0; i < n; i++) {
@@ -1141,8 +1309,10 @@ uint64_t hiz_compress_bound(const uint64_t dims[3])
     const uint64_t chunks = cdiv(N, 256);
     const uint64_t anchors = cdiv(dims[0], kAnchor) * cdiv(dims[1], kAnchor) * cdiv(dims[2], kAnchor);
     // header, lengths, chunk table, anchors, outlier indices (8 B) and values,
-    // payload of 32-bit codewords plus one padding word per chunk, section gaps
-    return kOffChunks + 4 * chunks + 4 * anchors + 12 * N + 4 * (N + chunks) + 64;
+    // payload of 32-bit codewords plus one padding word per chunk, the ratio
+    // mode's stage chunk sizes, section gaps
+    return kOffChunks + 4 * chunks + 4 * anchors + 12 * N + 4 * (N + chunks) +
+           4 * cdiv(4 * (N + chunks), kLcChunk) + 96;
 }
 
 uint64_t hiz_workspace_bound(const uint64_t dims[3])
@@ -1168,14 +1338,36 @@ uint64_t hiz_workspace_bound(const uint64_t dims[3])
         const uint64_t nt = (dims[0] / kAnchor) * (dims[1] / kAnchor) * (dims[2] / kAnchor / tz);
         coarse = std::max(coarse, nt * (4 * coarse_values_per_tile(tz) + coarse_codes_per_tile(tz)));
     }
-    const uint64_t comp = per_job + N + 16 * groups + 16 * chunks + 8 * mm + coarse;
-    const uint64_t dec = per_job + sizeof(DecTables) + N + 8 * cdiv(chunks, 256) + coarse;
+    // the lossless pipelines: reordered code sequence, the ratio mode's
+    // payload, stage and outlier-unit look-back words (with their gaps)
+    const uint64_t lc = cdiv(4 * (N + chunks), kLcChunk);
+    const uint64_t pipes = N + 4 * (N + chunks) + 16 * lc + 4 * 256;
+    const uint64_t comp = per_job + N + 16 * groups + 16 * chunks + 8 * mm + coarse + pipes;
+    const uint64_t dec = per_job + sizeof(DecTables) + N + 8 * cdiv(chunks, 256) + coarse + pipes;
     return std::max(comp, dec);
 }
 
 } // extern "C"
 
 namespace hiz {
+// Pinned staging of a context for batches of up to n fields, allocated now so
+// that no later call of that size reallocates it.
+hiz_status ctx_reserve_pinned(hiz_ctx *c, int n)
+{
+    const uint64_t jobs = ((sizeof(Job) * (uint64_t)n + 255) & ~uint64_t(255)) +
+                          (uint64_t)kResultBytes * n + 256;
+    return ensure_pinned(c, std::max<uint64_t>(jobs, (uint64_t)kOffChunks * n));
+}
+
+// Decompression submit with the streams' header bytes already on the host.
+hiz_status ctx_decompress_submit_hdrs(hiz_ctx *c, int n, const void *const *d_ins,
+                                      const uint64_t *in_sizes, float *const *d_fields,
+                                      const uint64_t *field_caps, hipStream_t s,
+                                      const uint8_t *h_hdrs)
+{
+    return submit_decompress(c, n, d_ins, in_sizes, d_fields, field_caps, s, h_hdrs);
+}
+
 uint64_t workspace_bound_points(uint64_t n)
 {
     const uint64_t d[3] = {n, 1, 1};

@@ -6,13 +6,19 @@
 // allocation happens while requests are served and codebooks, tables and code
 // buffers stay resident. A scheduler thread runs the loop of serve.h: a free
 // slot takes the next batch of waiting requests that fits its workspace and
-// enqueues it with the batched submit entry points; the slot's completion is
-// polled without blocking, so batches on different slots overlap on the GPU.
+// enqueues it with the batched submit entry points, followed on the slot's
+// stream by a host callback that wakes the loop when the batch is done; the
+// loop also wakes on every submit and never waits for the device itself, so
+// batches on different slots overlap on the GPU. Each slot's pinned staging is
+// reserved for max_batch requests at creation, and a decompression request's
+// header bytes are read on the submitting thread, so a batch submit never
+// synchronizes.
 #include "hiz.h"
 #include "hiz_internal.h"
 #include "serve.h"
 
 #include <chrono>
+#include <algorithm>
 #include <condition_variable>
 #include <cstring>
 #include <mutex>
@@ -30,6 +36,32 @@ double clock_s()
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Wakes the scheduling loop: on a submit, and from a stream host callback when
+// a batch completes on the device.
+struct Waker {
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    bool kick = false;
+
+    void wake()
+    {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            kick = true;
+        }
+        cv.notify_one();
+    }
+};
+
+void wake_from_stream(void *w) { static_cast<Waker *>(w)->wake(); }
+
+// A request's arguments, with the header bytes of a stream to decompress.
+struct Pending {
+    hiz_request r;
+    uint8_t hdr[hiz::kOffChunks];
+};
+
 // The GPU side of the scheduler: batched submits on per-slot contexts.
 struct GpuDevice {
     struct Slot {
@@ -46,7 +78,8 @@ struct GpuDevice {
     hiz_params params;
     std::vector<Slot> slots;
     std::mutex args_mu;
-    std::unordered_map<uint64_t, hiz_request> args; // payload key -> request
+    std::unordered_map<uint64_t, Pending> args; // payload key -> request
+    Waker *waker = nullptr;
 
     double now() { return clock_s(); }
 
@@ -70,10 +103,16 @@ struct GpuDevice {
             return false;
         }
         std::vector<hiz_request> rq(n);
+        std::vector<uint8_t> hdrs;
         {
             std::lock_guard<std::mutex> g(args_mu);
+            if (batch[0]->op == HIZ_OP_DECOMPRESS)
+                hdrs.resize((size_t)hiz::kOffChunks * n);
             for (int i = 0; i < n; i++) {
-                rq[i] = args[batch[i]->payload];
+                const Pending &p = args[batch[i]->payload];
+                rq[i] = p.r;
+                if (!hdrs.empty())
+                    memcpy(&hdrs[(size_t)hiz::kOffChunks * i], p.hdr, hiz::kOffChunks);
                 args.erase(batch[i]->payload);
             }
         }
@@ -109,11 +148,13 @@ struct GpuDevice {
                 outs[i] = static_cast<float *>(rq[i].d_out);
                 caps[i] = rq[i].out_cap;
             }
-            rc = hiz_decompress_batch_submit(sl.ctx, n, ins.data(), in_sizes.data(), outs.data(),
-                                             caps.data(),
-                                             reinterpret_cast<hiz_stream_t>(sl.stream));
+            rc = hiz::ctx_decompress_submit_hdrs(sl.ctx, n, ins.data(), in_sizes.data(),
+                                                 outs.data(), caps.data(), sl.stream,
+                                                 hdrs.data());
         }
         sl.submit_rc = rc;
+        if (rc == HIZ_OK && waker)
+            hipLaunchHostFunc(sl.stream, wake_from_stream, waker);
         return rc == HIZ_OK;
     }
 
@@ -143,11 +184,13 @@ struct hiz_server {
     hiz::serve::Policy policy;
     hiz::serve::Scheduler<GpuDevice> *sched = nullptr;
     std::thread worker;
-    std::mutex mu;
-    std::condition_variable cv;
-    bool stop = false;
+    Waker waker;
     uint64_t next_key = 1;
     std::string err;
+    // header reads of decompression requests (on the submitting thread)
+    std::mutex hdr_mu;
+    hipStream_t hdr_stream = nullptr;
+    uint8_t *hdr_pinned = nullptr;
 };
 
 namespace {
@@ -155,19 +198,21 @@ namespace {
 void serve_loop(hiz_server *S)
 {
     hipSetDevice(S->dev.device);
+    Waker &W = S->waker;
     while (true) {
-        const size_t made = S->sched->step();
-        if (S->sched->drained()) {
-            std::unique_lock<std::mutex> lk(S->mu);
-            if (S->stop)
-                break;
-            // nothing queued or running: sleep until a submit arrives
-            S->cv.wait_for(lk, std::chrono::milliseconds(5),
-                           [&] { return S->stop || !S->sched->drained(); });
-            continue;
+        {
+            std::lock_guard<std::mutex> g(W.mu);
+            W.kick = false;
         }
-        if (!made && S->sched->running() > 0)
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        const size_t made = S->sched->step();
+        std::unique_lock<std::mutex> lk(W.mu);
+        if (S->sched->drained() && W.stop)
+            break;
+        if (made)
+            continue;
+        // nothing changed: sleep until a submit or a batch completion wakes
+        // the loop (the timeout only guards against a lost wake-up)
+        W.cv.wait_for(lk, std::chrono::milliseconds(2), [&] { return W.kick || W.stop; });
     }
 }
 
@@ -220,6 +265,27 @@ hiz_status hiz_server_create(int device, int slots, uint64_t mem_budget, int max
             return rc;
         }
     }
+    hiz_status rc = HIZ_OK;
+    for (GpuDevice::Slot &sl : S->dev.slots)
+        if (rc == HIZ_OK)
+            rc = hiz::ctx_reserve_pinned(sl.ctx, max_batch);
+    if (rc == HIZ_OK && hipStreamCreateWithFlags(&S->hdr_stream, hipStreamNonBlocking) != hipSuccess)
+        rc = HIZ_ERR_HIP;
+    if (rc == HIZ_OK && hipHostMalloc((void **)&S->hdr_pinned, hiz::kOffChunks,
+                                      hipHostMallocDefault) != hipSuccess)
+        rc = HIZ_ERR_NOMEM;
+    if (rc != HIZ_OK) {
+        hipGetLastError();
+        for (GpuDevice::Slot &o : S->dev.slots) {
+            hipStreamDestroy(o.stream);
+            hiz_destroy(o.ctx);
+        }
+        if (S->hdr_stream)
+            hipStreamDestroy(S->hdr_stream);
+        delete S;
+        return rc;
+    }
+    S->dev.waker = &S->waker;
     S->sched = new hiz::serve::Scheduler<GpuDevice>(S->dev, slots, S->policy);
     S->worker = std::thread(serve_loop, S);
     *out = S;
@@ -249,6 +315,23 @@ hiz_status hiz_server_submit(hiz_server *S, const hiz_request *r)
     }
     if (need == 0)
         return HIZ_ERR_ARG;
+    Pending p;
+    p.r = *r;
+    memset(p.hdr, 0, sizeof(p.hdr));
+    if (r->op == HIZ_OP_DECOMPRESS) {
+        // the stream's header and code lengths, read here so that the batch
+        // submit on the scheduler thread never waits for the device
+        const size_t nh = (size_t)std::min<uint64_t>(r->in_size, hiz::kOffChunks);
+        std::lock_guard<std::mutex> g(S->hdr_mu);
+        hipSetDevice(S->dev.device);
+        if (hipMemcpyAsync(S->hdr_pinned, r->d_in, nh, hipMemcpyDeviceToHost, S->hdr_stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(S->hdr_stream) != hipSuccess) {
+            hipGetLastError();
+            return HIZ_ERR_HIP;
+        }
+        memcpy(p.hdr, S->hdr_pinned, nh);
+    }
     hiz::serve::Req q;
     q.id = r->id;
     q.op = r->op;
@@ -256,10 +339,10 @@ hiz_status hiz_server_submit(hiz_server *S, const hiz_request *r)
     {
         std::lock_guard<std::mutex> g(S->dev.args_mu);
         q.payload = S->next_key++;
-        S->dev.args[q.payload] = *r;
+        S->dev.args[q.payload] = p;
     }
     S->sched->submit(q);
-    S->cv.notify_one();
+    S->waker.wake();
     return HIZ_OK;
 }
 
@@ -315,13 +398,11 @@ void hiz_server_destroy(hiz_server *S)
     if (!S)
         return;
     {
-        std::lock_guard<std::mutex> g(S->mu);
-        S->stop = true;
+        std::lock_guard<std::mutex> g(S->waker.mu);
+        S->waker.stop = true;
     }
-    S->cv.notify_one();
-    // finish what was submitted before stopping the loop
-    while (!S->sched->drained())
-        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    S->waker.cv.notify_one();
+    // the loop finishes what was submitted before it stops
     if (S->worker.joinable())
         S->worker.join();
     delete S->sched;
@@ -333,6 +414,10 @@ void hiz_server_destroy(hiz_server *S)
         if (sl.ctx)
             hiz_destroy(sl.ctx);
     }
+    if (S->hdr_stream)
+        hipStreamDestroy(S->hdr_stream);
+    if (S->hdr_pinned)
+        hipHostFree(S->hdr_pinned);
     delete S;
 }
 

@@ -15,8 +15,9 @@ LIB_PATH = os.path.join(HERE, "libhiz.so")
 
 OK, ERR_ARG, ERR_NONFINITE, ERR_BUFSZ, ERR_CORRUPT, ERR_NOMEM, ERR_HIP = range(7)
 ABS, REL = 0, 1
-LINEAR, CUBIC = 0, 1
+LINEAR, CUBIC, NATURAL = 0, 1, 2
 MD, SEQ = 0, 1
+PIPE_HUFFMAN, PIPE_TP, PIPE_CR = 0, 1, 2
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NONFINITE", 3: "ERR_BUFSZ", 4: "ERR_CORRUPT",
            5: "ERR_NOMEM", 6: "ERR_HIP"}
 
@@ -33,7 +34,7 @@ OP_COMPRESS, OP_DECOMPRESS = 0, 1
 
 class Params(C.Structure):
     _fields_ = [("tune", C.c_int), ("level_cfg", (C.c_uint8 * 3) * 4), ("chunk", C.c_uint32),
-                ("tile_z", C.c_uint32)]
+                ("tile_z", C.c_uint32), ("pipeline", C.c_uint32), ("reorder", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -41,7 +42,8 @@ class Info(C.Structure):
                 ("eps", C.c_float), ("vmin", C.c_float), ("vmax", C.c_float),
                 ("constant", C.c_int), ("level_cfg", (C.c_uint8 * 3) * 4), ("chunk", C.c_uint32),
                 ("n_outliers", C.c_uint64), ("n_chunks", C.c_uint64),
-                ("payload_words", C.c_uint64), ("total_bytes", C.c_uint64)]
+                ("payload_words", C.c_uint64), ("total_bytes", C.c_uint64),
+                ("pipeline", C.c_int), ("reorder", C.c_int), ("lc_bytes", C.c_uint64)]
 
 
 class Request(C.Structure):
@@ -150,8 +152,11 @@ def workspace_bound(shape) -> int:
     return int(lib().hiz_workspace_bound(_dims(shape)))
 
 
-def make_params(tune=True, level_cfg=None, chunk=0, tile_z=0) -> Params:
+def make_params(tune=True, level_cfg=None, chunk=0, tile_z=0, pipeline=PIPE_HUFFMAN,
+                reorder=-1) -> Params:
     p = Params()
+    p.pipeline = int(pipeline)
+    p.reorder = int(reorder)
     p.tune = 1 if tune else 0
     cfg = level_cfg or ((CUBIC, MD, 0),) * 4
     for l in range(4):
@@ -195,6 +200,7 @@ def inspect(stream_bytes) -> dict:
         "level_cfg": tuple(tuple(int(info.level_cfg[l][k]) for k in range(3)) for l in range(4)),
         "chunk": info.chunk, "n_outliers": info.n_outliers, "n_chunks": info.n_chunks,
         "payload_words": info.payload_words, "total_bytes": info.total_bytes,
+        "pipeline": info.pipeline, "reorder": bool(info.reorder), "lc_bytes": info.lc_bytes,
     }
 
 
@@ -248,9 +254,12 @@ class Context:
     def compress(self, field, mode="rel", eb=1e-3, params=None, out=None, stream=None):
         """Compress a contiguous 3-D float32 CUDA tensor; returns a uint8 tensor view."""
         import torch
-        if field.dtype != torch.float32 or field.dim() != 3 or not field.is_cuda:
-            raise ValueError("compress needs a 3-D float32 tensor on a HIP device")
+        if field.dtype != torch.float32 or field.dim() not in (1, 2, 3) or not field.is_cuda:
+            raise ValueError("compress needs a 1-, 2- or 3-D float32 tensor on a HIP device")
+        # a 2-D field (H, W) is the 3-D field (1, H, W); a 1-D one (1, 1, W)
         field = field.contiguous()
+        while field.dim() < 3:
+            field = field.unsqueeze(0)
         n = field.numel()
         if out is None:
             cap = min(compress_bound(field.shape), 5 * n + (1 << 16))
@@ -267,8 +276,9 @@ class Context:
                                      out.numel(), params, sh)
         return out[:size]
 
-    def decompress(self, stream_t, out=None, stream=None):
-        """Decompress a uint8 CUDA tensor holding one stream; returns float32 (dx, dy, dz)."""
+    def decompress(self, stream_t, out=None, stream=None, squeeze=False):
+        """Decompress a uint8 CUDA tensor holding one stream; returns float32 (dx, dy, dz),
+        or with squeeze=True without the leading size-1 axes of a 2-D or 1-D field."""
         import torch
         if stream_t.dtype != torch.uint8 or not stream_t.is_cuda:
             raise ValueError("decompress needs a uint8 tensor on a HIP device")
@@ -280,7 +290,11 @@ class Context:
             out = torch.empty(shape, dtype=torch.float32, device=stream_t.device)
         self.decompress_ptr(stream_t.data_ptr(), stream_t.numel(), out.data_ptr(), out.numel(),
                             _stream_handle(stream))
-        return out.view(shape) if out.numel() == n else out
+        y = out.view(shape) if out.numel() == n else out
+        if squeeze and out.numel() == n:
+            while y.dim() > 1 and y.shape[0] == 1:
+                y = y[0]
+        return y
 
     # -- batches (C-ABI shaped: lists of device pointers) --
     def compress_batch_ptr(self, field_ptrs, shapes, modes, ebs, out_ptrs, out_caps,
@@ -502,6 +516,6 @@ def compress(field, mode="rel", eb=1e-3, params=None, out=None, stream=None):
     return default_context(field.device.index).compress(field, mode, eb, params, out, stream)
 
 
-def decompress(stream_t, out=None, stream=None):
+def decompress(stream_t, out=None, stream=None, squeeze=False):
     """X' = Dec(Z) on the tensor's device."""
-    return default_context(stream_t.device.index).decompress(stream_t, out, stream)
+    return default_context(stream_t.device.index).decompress(stream_t, out, stream, squeeze)

@@ -72,3 +72,24 @@ def test_inspect_constant_stream():
     r = O.compress(x, O.REL, 1e-3)
     info = hiz.inspect(r.stream.tobytes())
     assert info["constant"] and info["total_bytes"] == 132
+
+
+@pytest.mark.parametrize("pipeline,reorder", [(O.PIPE_TP, False), (O.PIPE_TP, True),
+                                              (O.PIPE_CR, True), (O.PIPE_CR, False),
+                                              (O.PIPE_HF, True)])
+def test_inspect_pipeline_streams(pipeline, reorder):
+    # the library's header parser accepts the oracle's streams of every
+    # lossless pipeline and reports their sections
+    x = G.grf((40, 33, 50), 3.0, 21)
+    r = O.compress(x, O.REL, 1e-3, chunk=512, pipeline=pipeline, reorder=reorder)
+    info = hiz.inspect(r.stream.tobytes())
+    assert info["pipeline"] == pipeline and info["reorder"] == reorder
+    assert info["total_bytes"] == r.stream.size
+    if pipeline == O.PIPE_HF:
+        assert info["lc_bytes"] == 0
+    else:
+        assert 0 < info["lc_bytes"] < r.stream.size
+    bad = r.stream.copy()
+    bad[54] = 7
+    with pytest.raises(hiz.HizError):
+        hiz.inspect(bad.tobytes())
