@@ -131,7 +131,8 @@ struct Job {
     // lossless pipeline and code order
     uint8_t pipe;        // PIPE_*
     uint8_t reorder;     // 1: the lossless stage sees the codes reordered by level
-    uint8_t pad4[6];
+    uint8_t pad4[2];
+    uint32_t chunk_req;  // chunk length asked for (recorded in a constant stream's header)
     uint8_t *seq;        // codes in the order the lossless stage sees (== codes if not reordered)
     uint8_t *hpay;       // ratio mode: Huffman payload in the workspace
     uint64_t hpay_cap;   // its capacity in bytes

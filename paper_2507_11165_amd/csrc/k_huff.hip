@@ -42,7 +42,8 @@ __device__ void write_header(uint8_t *h, const Job &J, uint8_t flags, float eps,
     for (int l = 0; l < kLevels; l++)
         for (int k = 0; k < 3; k++)
             h[H_CFG + 3 * l + k] = cfg[l][k];
-    put_le<uint32_t>(h + H_CHUNK, J.chunk);
+    // a constant stream records the chunk length asked for, whatever the pipeline
+    put_le<uint32_t>(h + H_CHUNK, (flags & kFlagConst) ? J.chunk_req : J.chunk);
     put_le<uint64_t>(h + H_NOUT, n_out);
     put_le<uint64_t>(h + H_TOTAL, total);
     put_le<uint64_t>(h + H_NCHUNKS, n_chunks);

@@ -583,6 +583,7 @@ hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode,
     J.ntz = (uint32_t)cdiv(J.nb[2], tz);
     J.n_anchors = (uint64_t)J.nb[0] * J.nb[1] * J.nb[2];
     J.chunk = chunk;
+    J.chunk_req = chunk;
     J.log2_chunk = (uint32_t)ilog2(chunk);
     J.n_chunks = cdiv(N, chunk);
     J.off_anchors = align16(kOffChunks + 4 * J.n_chunks);

@@ -24,7 +24,7 @@ if ROOT not in sys.path:
 
 SHAPES = [(64, 64, 64), (128, 128, 128), (192, 192, 192), (256, 256, 256), (100, 500, 500),
           (384, 384, 384), (512, 512, 512), (384, 96, 48), (48, 96, 384)]
-CHUNKS = [256, 512, 1024, 2048, 4096]
+CHUNKS = [256, 512, 1024, 2048]
 TILES = [1, 2, 4]
 
 
@@ -33,6 +33,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--eb", type=float, default=1e-3)
+    ap.add_argument("--shapes", type=str, default="",
+                    help="only these shapes, e.g. 512x512x512,64x64x64")
     args = ap.parse_args()
 
     import numpy as np
@@ -45,7 +47,10 @@ def main():
     ctx = hiz.Context(0)
     sh = hiz.C.c_void_p(torch.cuda.current_stream().cuda_stream)
     picks = []
-    for shape in SHAPES:
+    shapes = SHAPES
+    if args.shapes:
+        shapes = [tuple(int(v) for v in t.split("x")) for t in args.shapes.split(",")]
+    for shape in shapes:
         x = fieldgen.grf(shape, 11.0 / 3.0, 9000 + shape[0])
         N = x.size
         xd = torch.from_numpy(x).to(dev)
@@ -74,8 +79,19 @@ def main():
                 gbs = 8.0 * N / (ms * 1e-3) / 1e9
                 ratio = 4.0 * N / size
                 rows.append((chunk, tz, ms, gbs, ratio))
+                # per-kernel means of two more (profiled, untimed) steps
+                ctx.reset_profile()
+                ctx.set_profiling(True)
+                for _ in range(2):
+                    step()
+                torch.cuda.synchronize()
+                ctx.set_profiling(False)
+                prof = ctx.profile()
+                ks = " ".join(f"{k}={v[1] / max(v[0], 1) * 1e3:.1f}us" for k, v in sorted(prof.items())
+                              if k in ("encode", "decode", "predict_quant", "reconstruct", "coarse",
+                                       "coarse_rec"))
                 print(f"shape {shape} N {N} chunk {chunk} tile_z {tz} ms {ms:.4f} "
-                      f"GBps {gbs:.1f} ratio {ratio:.4f}", flush=True)
+                      f"GBps {gbs:.1f} ratio {ratio:.4f} {ks}", flush=True)
         best_ratio = max(r[4] for r in rows)
         ok = [r for r in rows if r[4] >= 0.99 * best_ratio]
         best = max(ok, key=lambda r: r[3])

@@ -270,9 +270,10 @@ def test_two_dimensional_climate_size(ctx):
 def test_two_dimensional_tensor_through_binding(ctx):
     # a 2-D tensor goes in as it is and comes back 2-D
     x = G.grf((1, 130, 250), 3.0, 62)
+    from paper_2507_11165_amd import hiz
     t = torch.from_numpy(x[0].copy()).to("cuda:0")
-    z = ctx.compress(t, "rel", 1e-3)
-    ref = O.compress(x, O.REL, 1e-3, debug=False)
+    z = ctx.compress(t, "rel", 1e-3, hiz.make_params(tune=True, chunk=512))
+    ref = O.compress(x, O.REL, 1e-3, tune=True, chunk=512, debug=False)
     assert np.array_equal(z.cpu().numpy(), ref.stream)
     y = ctx.decompress(z, squeeze=True)
     assert tuple(y.shape) == (130, 250)
