@@ -136,6 +136,25 @@ hiz_status hiz_compress(hiz_ctx *ctx, const float *d_field, const uint64_t dims[
                         void *d_out, uint64_t out_cap, uint64_t *out_size,
                         hiz_stream_t stream);
 
+/* hiz_compress without any allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, result and errors as hiz_compress, and the
+ * same stream bytes. Its workspace is a fixed 256 MiB array in device memory
+ * that every GPU the library runs on holds from the library's first use
+ * until the process ends (its address on the device is looked up by
+ * hiz_create); the call itself makes no device, pinned or host allocation,
+ * uses no HIP graph and records no profiling events. A field whose workspace
+ * exceeds the array (about 1.9 bytes per point with the Huffman pipeline,
+ * so up to about 512^3 points; several times more with HIZ_PIPE_CR or
+ * reordering) is rejected with HIZ_ERR_ARG before any device work. Every call
+ * on one GPU, from any context, shares that GPU's array: calls that overlap
+ * in time on one GPU (other threads, other streams) race and must be
+ * serialised by the caller. Synchronizes `stream`. */
+hiz_status hiz_compress_noalloc(hiz_ctx *ctx, const float *d_field, const uint64_t dims[3],
+                                hiz_eb_mode mode, double eb, const hiz_params *params,
+                                void *d_out, uint64_t out_cap, uint64_t *out_size,
+                                hiz_stream_t stream);
+
 /* X' = Dec(Z) (Sec. 3.1). Reads the stream d_in (in_size bytes), writes
  * dims[0]*dims[1]*dims[2] floats to d_field (capacity field_cap elements).
  * If dims_out is not NULL it receives the field's dims. Synchronizes `stream`.

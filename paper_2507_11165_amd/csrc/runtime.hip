@@ -99,6 +99,7 @@ struct hiz_ctx {
     uint64_t graph_builds = 0, graph_replays = 0;
     hipEvent_t done = nullptr;
     Batch batch;
+    uint8_t *scratch = nullptr; // this device's copy of the allocation-free call's scratch array
 };
 
 namespace {
@@ -1235,6 +1236,106 @@ hiz_status finish(hiz_ctx *c, uint64_t *sizes, uint64_t *dims, hiz_status *statu
     return first;
 }
 
+
+// ---- allocation-free compression -------------------------------------------
+// The workspace of hiz_compress_noalloc: a fixed array in device memory that
+// every GPU running the library holds once, from the code object's load until
+// the process ends. In host code `scratch` names a host-side stand-in, never
+// the device memory: the address each device holds it at is looked up once
+// per device (hiz_create, with that device current) and only that address is
+// used afterwards.
+constexpr uint64_t kScratchBytes = 256ull << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `device` (resolved once).
+hiz_status resolve_scratch(int device, uint8_t **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return HIZ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            hipGetLastError();
+            return HIZ_ERR_HIP;
+        }
+        g_scratch_ptr[device] = static_cast<uint8_t *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return HIZ_OK;
+}
+
+// One compression through the scratch array: the same plan, layout and launch
+// sequence as hiz_compress, with no device, pinned or heap allocation (the
+// Job table goes up from the pinned block the context allocated at creation,
+// and profiling and graphs are skipped).
+hiz_status compress_noalloc(hiz_ctx *c, const float *d_field, const uint64_t dims[3], int mode,
+                            double eb, const hiz_params *params, void *d_out, uint64_t out_cap,
+                            uint64_t *out_size, hipStream_t s)
+{
+    c->err.clear();
+    if (c->batch.pending)
+        return fail(c, HIZ_ERR_ARG, "the previous batch on this context is not finished");
+    if (!c->scratch)
+        return fail(c, HIZ_ERR_HIP, "the scratch array's device address is not known");
+    hiz_params p;
+    int tz;
+    hiz_status rc = resolve_params(c, params, p, tz);
+    if (rc)
+        return rc;
+    HIP_TRY(c, hipSetDevice(c->device));
+    Job J;
+    const char *m = "";
+    rc = plan_compress(d_field, dims, mode, eb, p, tz, d_out, out_cap, J, m);
+    if (rc)
+        return fail(c, rc, "%s", m);
+    // the same sections as a one-field batch, laid out from the scratch base
+    Arena A;
+    const uint64_t o_jobs = A.take(sizeof(Job));
+    const uint64_t o_cnt = A.take(sizeof(Counters));
+    const uint64_t o_res = A.take(kResultBytes);
+    Totals T;
+    Sections o;
+    take_sections(A, J, false, tz, T, o);
+    if (!totals_fit(T))
+        return fail(c, HIZ_ERR_ARG, "field too large for one launch");
+    if (A.off > kScratchBytes)
+        return fail(c, HIZ_ERR_ARG,
+                    "field needs %llu bytes of workspace; the allocation-free call holds at most "
+                    "%llu (use hiz_compress)",
+                    (unsigned long long)A.off, (unsigned long long)kScratchBytes);
+    const uint64_t job_bytes = (sizeof(Job) + 255) & ~uint64_t(255);
+    if (job_bytes + kResultBytes > c->pinned_size)
+        return fail(c, HIZ_ERR_ARG, "the context's staging block is too small");
+    bind_sections(c->scratch, J, false, o);
+    memcpy(c->pinned, &J, sizeof(Job));
+    Layout L;
+    L.d_jobs = reinterpret_cast<Job *>(c->scratch + o_jobs);
+    L.d_cnt = reinterpret_cast<Counters *>(c->scratch + o_cnt);
+    L.d_res = c->scratch + o_res;
+    L.h_res = c->pinned + job_bytes;
+    L.h_jobs = c->pinned;
+    enqueue_compress(c, L, 1, T, tz, s, false);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(s));
+    FieldState res;
+    memcpy(&res, L.h_res, kResultBytes);
+    if (res.flags & ST_NONFINITE)
+        return fail(c, HIZ_ERR_NONFINITE, "field holds NaN or Inf");
+    if (res.flags & ST_CORRUPT)
+        return fail(c, HIZ_ERR_HIP, "internal consistency check failed");
+    *out_size = res.total_bytes;
+    if ((res.flags & ST_OVERFLOW) || res.total_bytes > out_cap)
+        return fail(c, HIZ_ERR_BUFSZ, "output needs %llu bytes, capacity is %llu",
+                    (unsigned long long)res.total_bytes, (unsigned long long)out_cap);
+    return HIZ_OK;
+}
+
 } // namespace
 
 // ===========================================================================
@@ -1271,6 +1372,19 @@ hiz_status hiz_create(int device, size_t workspace_bytes, hiz_ctx **out)
         delete c;
         return HIZ_ERR_NOMEM;
     }
+    // set-up for hiz_compress_noalloc: the scratch array's address on this
+    // device, launch-grid queries, and room for any error message, so that
+    // the call itself allocates nothing
+    if (resolve_scratch(device, &c->scratch) != HIZ_OK) {
+        hipFree(c->ws);
+        hipHostFree(c->pinned);
+        delete c;
+        return HIZ_ERR_HIP;
+    }
+    for (int tz = 1; tz <= 4; tz *= 2)
+        predict_grid(c, tz, 1, false);
+    encode_grid(c);
+    c->err.reserve(512);
     *out = c;
     return HIZ_OK;
 }
@@ -1443,6 +1557,19 @@ hiz_status hiz_compress(hiz_ctx *c, const float *d_field, const uint64_t dims[3]
     hiz_status rc = submit_compress(c, 1, &d_field, dims, &m, &eb, params, outs, &out_cap,
                                     reinterpret_cast<hipStream_t>(stream));
     return rc ? rc : finish(c, out_size, nullptr, nullptr);
+}
+
+hiz_status hiz_compress_noalloc(hiz_ctx *c, const float *d_field, const uint64_t dims[3],
+                                hiz_eb_mode mode, double eb, const hiz_params *params, void *d_out,
+                                uint64_t out_cap, uint64_t *out_size, hiz_stream_t stream)
+{
+    if (!c)
+        return HIZ_ERR_ARG;
+    if (!out_size || !dims)
+        return fail(c, HIZ_ERR_ARG, "NULL argument");
+    *out_size = 0;
+    return compress_noalloc(c, d_field, dims, (int)mode, eb, params, d_out, out_cap, out_size,
+                            reinterpret_cast<hipStream_t>(stream));
 }
 
 hiz_status hiz_decompress(hiz_ctx *c, const void *d_in, uint64_t in_size, float *d_field,

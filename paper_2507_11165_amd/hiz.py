@@ -28,7 +28,7 @@ SYMBOLS = ["hiz_create", "hiz_destroy", "hiz_last_error", "hiz_compress_bound",
            "hiz_decompress_batch_submit", "hiz_batch_ready", "hiz_batch_finish", "hiz_set_graphs",
            "hiz_graph_stats", "hiz_server_create", "hiz_server_submit", "hiz_server_poll",
            "hiz_server_drain", "hiz_server_get_stats", "hiz_server_clock", "hiz_server_destroy",
-           "hiz_set_profiling", "hiz_get_profile", "hiz_reset_profile"]
+           "hiz_set_profiling", "hiz_get_profile", "hiz_reset_profile", "hiz_compress_noalloc"]
 OP_COMPRESS, OP_DECOMPRESS = 0, 1
 
 
@@ -99,6 +99,7 @@ def lib():
             L.hiz_compress.argtypes = [C.c_void_p, C.c_void_p, u64p, C.c_int, C.c_double,
                                        C.POINTER(Params), C.c_void_p, C.c_uint64, u64p,
                                        C.c_void_p]
+            L.hiz_compress_noalloc.argtypes = L.hiz_compress.argtypes
             L.hiz_decompress.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                          C.c_uint64, u64p, C.c_void_p]
             L.hiz_inspect.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Info)]
@@ -240,6 +241,19 @@ class Context:
                                 stream_handle)
         if rc:
             raise self._err(rc, "compress", int(size.value))
+        return int(size.value)
+
+    def compress_noalloc_ptr(self, field_ptr, shape, mode, eb, out_ptr, out_cap, params=None,
+                             stream_handle=None) -> int:
+        """hiz_compress_noalloc: the same stream as compress_ptr, with the
+        library's fixed scratch array as workspace (nothing allocated)."""
+        size = C.c_uint64()
+        p = C.byref(params) if params is not None else None
+        rc = lib().hiz_compress_noalloc(self._h, C.c_void_p(field_ptr), _dims(shape), _mode(mode),
+                                        float(eb), p, C.c_void_p(out_ptr), int(out_cap),
+                                        C.byref(size), stream_handle)
+        if rc:
+            raise self._err(rc, "compress_noalloc", int(size.value))
         return int(size.value)
 
     def decompress_ptr(self, in_ptr, in_size, out_ptr, out_cap, stream_handle=None):
