@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--workload", choices=["turb512", "batch64", "serve"], default="turb512")
     ap.add_argument("--duration", type=float, default=2.0,
                     help="serve: seconds of the Poisson trace replayed")
+    ap.add_argument("--graphs", type=int, default=0,
+                    help="1: replay each call's launch sequence from a HIP graph")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB: the reference "
                          "kernel of known traffic that scales FETCH_SIZE / WRITE_SIZE counters")
@@ -296,6 +298,7 @@ def main():
     shape = x.shape
     xd = torch.from_numpy(x).to(dev)
     ctx = hiz.Context(0)
+    ctx.set_graphs(bool(args.graphs))
     params = hiz.make_params(tune=True, chunk=args.chunk, tile_z=args.tile_z)
     cap = 5 * N + (1 << 20)
     zbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
@@ -344,9 +347,9 @@ def main():
     step_bytes = step_algorithmic_bytes(N, info, n_anchors)
     step_s = elapsed / args.steps
     # measured HBM bytes of one step: every kernel's counted traffic (all of
-    # them must have current counters; the table's 'coarse' pre-pass kernels
-    # and the Huffman encoder's two passes are listed under their own names)
-    traffic_names = ["minmax", "coarse", "predict_quant", "enc_sizes", "enc_pack", "decode",
+    # them must have current counters; the coarse pre-pass kernels are listed
+    # under their own names)
+    traffic_names = ["minmax", "coarse", "predict_quant", "encode", "decode",
                      "coarse_rec", "reconstruct"]
     tr = [measured_traffic(k) if current else None for k in traffic_names]
     step_traffic = sum(tr) if all(tr) else None
@@ -354,7 +357,8 @@ def main():
     res = base_line(value, args.steps, args.warmup, round(step_s * 1e3, 4), {
         "workload": "single 512x512x512 FP32 field, GRF k^-11/3 + 1% white noise, rel eb 1e-3",
         "dims": list(shape), "eb_mode": "rel", "eb": args.eb,
-        "chunk": info["chunk"], "tile_z": args.tile_z or 2, "level_cfg": info["level_cfg"],
+        "chunk": info["chunk"], "tile_z": args.tile_z or "launch table (2 at 512^3)",
+        "level_cfg": info["level_cfg"],
     })
     res.update(field_summary(x, m))
     res.pop("level_cfg")

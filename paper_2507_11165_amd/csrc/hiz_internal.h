@@ -131,7 +131,8 @@ struct Job {
     // lossless pipeline and code order
     uint8_t pipe;        // PIPE_*
     uint8_t reorder;     // 1: the lossless stage sees the codes reordered by level
-    uint8_t pad4[2];
+    uint8_t tz;          // tile depth along z (1, 2 or 4 blocks)
+    uint8_t pad4;
     uint32_t chunk_req;  // chunk length asked for (recorded in a constant stream's header)
     uint8_t *seq;        // codes in the order the lossless stage sees (== codes if not reordered)
     uint8_t *hpay;       // ratio mode: Huffman payload in the workspace
@@ -152,14 +153,18 @@ struct JobList {
     uint64_t total; // total units of the launch's work kind
 };
 
+// Tile depths along z: 1, 2 or 4 blocks (index 0, 1, 2).
+constexpr int kTileDepths = 3;
+
 // Counters reset at the start of every call.
 struct Counters {
     uint32_t enc_next;
     uint32_t dec_next;
-    uint32_t tile_next[8]; // per XCD: tiles claimed by predict / reconstruct
     uint32_t lc_next;      // bitwise-redundancy chunks
     uint32_t ou_next;      // outlier units
-    uint32_t pad[4];
+    // per tile depth (1, 2, 4) and XCD: tiles claimed by predict / reconstruct
+    uint32_t tile_next[kTileDepths][8];
+    uint32_t pad[12];
 };
 
 // ---- kernel launchers (each defined next to its kernel) ----
@@ -172,8 +177,11 @@ void launch_minmax(const Job *d_jobs, int njobs, uint64_t total, int grid, hipSt
 void launch_eps(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_tune(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s);
 void launch_tune_pick(const Job *d_jobs, int njobs, hipStream_t s);
-void launch_predict(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
-                    Counters *cnt, hipStream_t s);
+// The tile kernels run over the tiles [lo, hi) of the work list, which belong
+// to the njobs jobs at d_jobs (all of tile depth tile_z); ctr: their eight
+// claim counters.
+void launch_predict(const Job *d_jobs, int njobs, uint64_t lo, uint64_t hi, int tile_z, int grid,
+                    uint32_t *ctr, hipStream_t s);
 int predict_blocks_per_cu(int tile_z);
 void launch_codebook(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_encode(const Job *d_jobs, int njobs, uint64_t total_chunks, uint64_t total_groups,
@@ -187,12 +195,12 @@ void launch_init_decompress(const Job *d_jobs, int njobs, uint64_t max_blocks, C
 void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_decode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, hipStream_t s);
 void launch_scatter(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s);
-void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
-                        Counters *cnt, hipStream_t s);
+void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t lo, uint64_t hi, int tile_z,
+                        int grid, uint32_t *ctr, hipStream_t s);
 // Levels of stride 8, 4, 2 of every full tile on its grid of even points
 // (one wave per tile), ahead of k_predict / k_reconstruct.
-void launch_coarse(const Job *d_jobs, int njobs, uint64_t total, int tile_z, bool compress,
-                   hipStream_t s);
+void launch_coarse(const Job *d_jobs, int njobs, uint64_t lo, uint64_t hi, int tile_z,
+                   bool compress, hipStream_t s);
 // Values (4 bytes each) and codes of one tile's even-point grid.
 uint64_t coarse_values_per_tile(int tile_z);
 uint64_t coarse_codes_per_tile(int tile_z);

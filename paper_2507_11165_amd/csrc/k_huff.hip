@@ -413,12 +413,11 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
 __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, int njobs,
                                                   uint64_t total)
 {
-    __shared__ uint32_t s_code[kEncWaves][256];
-    __shared__ uint8_t s_len[kEncWaves][256];
+    // per wave: (code, length) of every symbol, and the pack buffer
+    __shared__ uint2 s_cl[kEncWaves][256];
     __shared__ uint32_t s_buf[kEncWaves][kEncBuf];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t *code = s_code[wv];
-    uint8_t *len = s_len[wv];
+    uint2 *cl = s_cl[wv];
     uint32_t *buf = s_buf[wv];
     for (int k = lane; k < kEncBuf; k += 64)
         buf[k] = 0;
@@ -431,10 +430,8 @@ __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, 
         if (st->flags & (ST_CONST | ST_NONFINITE))
             continue;
         if (ji != cur) {
-            for (int k = lane; k < 256; k += 64) {
-                code[k] = st->cb_code[k];
-                len[k] = st->cb_len[k];
-            }
+            for (int k = lane; k < 256; k += 64)
+                cl[k] = make_uint2(st->cb_code[k], st->cb_len[k]);
             cur = ji;
             wave_sync_lds();
         }
@@ -464,41 +461,50 @@ __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, 
             const int P = (sl + 63) / 64;
             const int n = max(0, min(P, sl - lane * P));
             const uint64_t gfirst = c0 + (uint64_t)sg * kEncSeg + (uint64_t)lane * P;
-            uint32_t r[4], mb, mz;
+            uint32_t r[4];
             load_lane_codes(src + sg * kEncSeg + lane * P, P, n, r);
-            lane_sizes(r, n, len, mb, mz);
+            // every symbol's (code, length) at once; lengths of absent
+            // symbols (past n) count zero
+            uint2 e[16];
+            uint32_t mb = 0, mz = 0;
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const uint32_t c = code_at(r, k);
+                e[k] = cl[c];
+                if (k >= n)
+                    e[k].y = 0;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                mb += e[k].y;
+                mz += (k < n) & (code_at(r, k) == 0);
+            }
             const uint32_t ib_incl = wave_incl_scan(mb);
             const uint32_t iz_incl = wave_incl_scan(mz);
             const uint32_t seg_bits = (uint32_t)__shfl((int)ib_incl, 63, 64);
             const uint32_t seg_zero = (uint32_t)__shfl((int)iz_incl, 63, 64);
-            const uint64_t wb = sb >> 5;
-            const uint32_t orel = (uint32_t)(sb & 31) + (ib_incl - mb);
-            uint32_t cw = orel >> 5, sh = orel & 31, curw = 0;
-            uint64_t zpos = zpos0 + (iz_incl - mz);
+            const uint64_t wseg = sb >> 5;
+            // bit of this lane's first code, relative to the buffer's word 0
+            uint32_t p = (uint32_t)(sb & 31) + (ib_incl - mb);
+            // each code is OR-ed into the (one or two) words it covers; codes
+            // are independent of one another
 #pragma unroll
             for (int k = 0; k < 16; k++) {
-                if (k >= n)
-                    break;
-                const uint32_t c = code_at(r, k);
-                const uint32_t L = len[c], cd = code[c];
-                if (sh + L < 32) {
-                    curw |= cd << (32 - sh - L);
-                    sh += L;
-                } else if (sh + L == 32) {
-                    curw |= cd;
-                    atomicOr(&buf[cw], curw);
-                    cw++;
-                    curw = 0;
-                    sh = 0;
-                } else {
-                    const uint32_t rr = sh + L - 32;
-                    curw |= cd >> rr;
-                    atomicOr(&buf[cw], curw);
-                    cw++;
-                    curw = cd << (32 - rr);
-                    sh = rr;
+                const uint32_t L = e[k].y;
+                if (L) {
+                    const uint32_t w = p >> 5, sh = p & 31;
+                    const uint64_t v = (uint64_t)e[k].x << (64 - sh - L);
+                    atomicOr(&buf[w], (uint32_t)(v >> 32));
+                    if ((uint32_t)v)
+                        atomicOr(&buf[w + 1], (uint32_t)v);
                 }
-                if (c == 0 && outl) {
+                p += L;
+            }
+            if (outl && mz) {
+                uint64_t zpos = zpos0 + (iz_incl - mz);
+                for (int k = 0; k < n; k++) {
+                    if (code_at(r, k) != 0)
+                        continue;
                     const uint64_t gi = gfirst + k;
                     if (o_idx + (zpos + 1) * ib <= cap) {
                         if (ib == 4)
@@ -511,13 +517,11 @@ __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, 
                     zpos++;
                 }
             }
-            if (sh > 0)
-                atomicOr(&buf[cw], curw);
             wave_sync_lds();
             const uint64_t se = sb + seg_bits;
-            const uint32_t nfull = (uint32_t)((se >> 5) - wb);
+            const uint32_t nfull = (uint32_t)((se >> 5) - wseg);
             for (uint32_t k = lane; k < nfull; k += 64) {
-                const uint64_t gw = wbase + wb + k;
+                const uint64_t gw = wbase + wseg + k;
                 if (gw < pay_words_cap)
                     payload[gw] = buf[k];
             }
@@ -607,10 +611,13 @@ void launch_init_decompress(const Job *d_jobs, int njobs, uint64_t max_blocks, C
 
 // Decoder tables from the stored code lengths: canonical codes, a direct
 // lookup table for codes up to kLutBits bits and per-length ranges for the
-// longer ones.
+// longer ones. The lookup table is built by kDecTableParts workgroups per
+// field, one slice each; the first also writes the per-length tables.
+constexpr int kDecTableParts = 8;
+
 __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs, int njobs)
 {
-    const Job &J = jobs[blockIdx.x];
+    const Job &J = jobs[blockIdx.y];
     DecTables *dt = J.dt;
     __shared__ uint8_t len[256];
     __shared__ uint32_t blc[kMaxCodeLen + 2];
@@ -638,10 +645,11 @@ __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs
             if (blc[b])
                 maxlen = (uint32_t)b;
         }
-        dt->maxlen = maxlen;
+        if (blockIdx.x == 0)
+            dt->maxlen = maxlen;
     }
     __syncthreads();
-    if (t <= kMaxCodeLen) {
+    if (blockIdx.x == 0 && t <= kMaxCodeLen) {
         dt->first[t] = first[t];
         dt->count[t] = blc[t];
         dt->index[t] = index[t];
@@ -653,9 +661,12 @@ __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs
         s_sorted[index[L] + k] = (uint8_t)t;
     }
     __syncthreads();
-    dt->sorted[t] = s_sorted[t];
-    // every table entry by itself: the shortest code that prefixes its index
-    for (uint32_t e = t; e < (1u << kLutBits); e += 256) {
+    if (blockIdx.x == 0)
+        dt->sorted[t] = s_sorted[t];
+    // this part's table entries, each by itself: the shortest code that
+    // prefixes its index
+    constexpr uint32_t kPart = (1u << kLutBits) / kDecTableParts;
+    for (uint32_t e = blockIdx.x * kPart + t; e < (blockIdx.x + 1) * kPart; e += 256) {
         uint16_t v = 0;
         for (int b = 1; b <= kLutBits; b++) {
             const uint32_t c = e >> (kLutBits - b);
@@ -670,7 +681,7 @@ __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs
 
 void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dec_tables, dim3(njobs), dim3(256), 0, s, d_jobs, njobs);
+    hipLaunchKernelGGL(k_dec_tables, dim3(kDecTableParts, njobs), dim3(256), 0, s, d_jobs, njobs);
 }
 
 // One thread per chunk; a workgroup takes 256 consecutive chunks, finds its

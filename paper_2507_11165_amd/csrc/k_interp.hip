@@ -755,18 +755,20 @@ template <int TZ> __device__ __forceinline__ bool prepass_tile(const Geo &g)
 constexpr int kClaimThread = 192;
 constexpr int kStoreThreads = 192; // threads of a tile's output stores
 struct TileQueue {
-    uint64_t total;
-    uint32_t *ctr; // eight counters, one per eighth
+    uint64_t base;  // first tile of the launch's range
+    uint64_t total; // tiles in the range
+    uint32_t *ctr;  // eight counters, one per eighth
     int home;      // this workgroup's XCD
     int k;         // eighths tried so far (thread 0)
     uint32_t ask;  // outstanding claim on eighth (home + k) & 7 (thread 0)
 };
 __device__ __forceinline__ uint64_t eighth_lo(uint64_t total, int x) { return total * x / 8; }
-__device__ __forceinline__ TileQueue tile_queue(uint64_t total, Counters *cnt)
+__device__ __forceinline__ TileQueue tile_queue(uint64_t lo, uint64_t hi, uint32_t *ctr)
 {
     TileQueue q;
-    q.total = total;
-    q.ctr = cnt->tile_next;
+    q.base = lo;
+    q.total = hi - lo;
+    q.ctr = ctr;
     q.home = (gridDim.x >= 8 && (gridDim.x & 7) == 0) ? (int)(blockIdx.x & 7) : 0;
     q.k = 0;
     q.ask = 0;
@@ -774,8 +776,8 @@ __device__ __forceinline__ TileQueue tile_queue(uint64_t total, Counters *cnt)
         q.ask = atomicAdd(&q.ctr[q.home], 1u);
     return q;
 }
-// Claiming thread: resolve the outstanding claim into a tile index (total = none
-// left) and ask for the following one.
+// Claiming thread: resolve the outstanding claim into a tile index (the
+// range's end = none left) and ask for the following one.
 __device__ __forceinline__ uint64_t next_tile(TileQueue &q)
 {
     while (q.k < 8) {
@@ -787,13 +789,13 @@ __device__ __forceinline__ uint64_t next_tile(TileQueue &q)
             // there and go first instead of holding up the end of the launch
             const uint64_t u = hi - 1 - q.ask;
             q.ask = atomicAdd(&q.ctr[x], 1u);
-            return u;
+            return q.base + u;
         }
         q.k++;
         if (q.k < 8)
             q.ask = atomicAdd(&q.ctr[(q.home + q.k) & 7], 1u);
     }
-    return q.total;
+    return q.base + q.total;
 }
 __device__ __forceinline__ uint64_t claim_tile(TileQueue &q, uint64_t *slot, int it)
 {
@@ -1089,7 +1091,7 @@ __device__ __forceinline__ void tile_place(const TileRegs<TZ> &f, float *__restr
 // ---------------------------------------------------------------------------
 template <int TZ>
 __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs, int njobs,
-                                                 uint64_t total, Counters *cnt)
+                                                 uint64_t lo, uint64_t total, uint32_t *ctr)
 {
     using TS = TileShape<TZ>;
     constexpr bool PF = kPrefetchTiles<TZ>;
@@ -1111,7 +1113,7 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
     int ftid = t;
     asm volatile("" : "+v"(ftid));
     TileRegs<TZ> f;
-    TileQueue tq = tile_queue(total, cnt);
+    TileQueue tq = tile_queue(lo, total, ctr);
     uint64_t u = claim_tile(tq, s_tile, 0);
     if (PF && u < total)
         tile_fetch<TZ>(f, jobs[find_job<WK_TILE>(jobs, njobs, u)], u, ftid);
@@ -1239,23 +1241,23 @@ __global__ __launch_bounds__(256, 3) void k_predict(const Job *__restrict__ jobs
     }
 }
 
-template <int TZ> static void launch_predict_t(const Job *d_jobs, int njobs, uint64_t total,
-                                              int grid, Counters *cnt, hipStream_t s)
+template <int TZ> static void launch_predict_t(const Job *d_jobs, int njobs, uint64_t lo,
+                                              uint64_t hi, int grid, uint32_t *ctr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_predict<TZ>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, total, cnt);
+    hipLaunchKernelGGL(k_predict<TZ>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, lo, hi, ctr);
 }
 
-void launch_predict(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
-                    Counters *cnt, hipStream_t s)
+void launch_predict(const Job *d_jobs, int njobs, uint64_t lo, uint64_t hi, int tile_z, int grid,
+                    uint32_t *ctr, hipStream_t s)
 {
-    if (total == 0)
+    if (hi <= lo)
         return;
     if (tile_z == 1)
-        launch_predict_t<1>(d_jobs, njobs, total, grid, cnt, s);
+        launch_predict_t<1>(d_jobs, njobs, lo, hi, grid, ctr, s);
     else if (tile_z == 4)
-        launch_predict_t<4>(d_jobs, njobs, total, grid, cnt, s);
+        launch_predict_t<4>(d_jobs, njobs, lo, hi, grid, ctr, s);
     else
-        launch_predict_t<2>(d_jobs, njobs, total, grid, cnt, s);
+        launch_predict_t<2>(d_jobs, njobs, lo, hi, grid, ctr, s);
 }
 
 int predict_blocks_per_cu(int tile_z)
@@ -1407,7 +1409,7 @@ __device__ __forceinline__ bool code_place(const CodeRegs<TZ> &f, uint8_t *__res
 // ---------------------------------------------------------------------------
 template <int TZ>
 __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ jobs, int njobs,
-                                                     uint64_t total, Counters *cnt)
+                                                     uint64_t lo, uint64_t total, uint32_t *ctr)
 {
     using TS = TileShape<TZ>;
     __shared__ float v[TS::NV];
@@ -1422,7 +1424,7 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
     int ftid = t;
     asm volatile("" : "+v"(ftid));
     CodeRegs<TZ> f;
-    TileQueue tq = tile_queue(total, cnt);
+    TileQueue tq = tile_queue(lo, total, ctr);
     uint64_t u = claim_tile(tq, s_tile, 0);
     if (u < total)
         code_fetch<TZ>(f, jobs[find_job<WK_TILE>(jobs, njobs, u)], u, ftid);
@@ -1514,24 +1516,24 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
     }
 }
 
-template <int TZ> static void launch_reconstruct_t(const Job *d_jobs, int njobs, uint64_t total,
-                                                  int grid, Counters *cnt, hipStream_t s)
+template <int TZ> static void launch_reconstruct_t(const Job *d_jobs, int njobs, uint64_t lo,
+                                                  uint64_t hi, int grid, uint32_t *ctr,
+                                                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reconstruct<TZ>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, total,
-                       cnt);
+    hipLaunchKernelGGL(k_reconstruct<TZ>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, lo, hi, ctr);
 }
 
-void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t total, int tile_z, int grid,
-                        Counters *cnt, hipStream_t s)
+void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t lo, uint64_t hi, int tile_z,
+                        int grid, uint32_t *ctr, hipStream_t s)
 {
-    if (total == 0)
+    if (hi <= lo)
         return;
     if (tile_z == 1)
-        launch_reconstruct_t<1>(d_jobs, njobs, total, grid, cnt, s);
+        launch_reconstruct_t<1>(d_jobs, njobs, lo, hi, grid, ctr, s);
     else if (tile_z == 4)
-        launch_reconstruct_t<4>(d_jobs, njobs, total, grid, cnt, s);
+        launch_reconstruct_t<4>(d_jobs, njobs, lo, hi, grid, ctr, s);
     else
-        launch_reconstruct_t<2>(d_jobs, njobs, total, grid, cnt, s);
+        launch_reconstruct_t<2>(d_jobs, njobs, lo, hi, grid, ctr, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1549,7 +1551,7 @@ void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t total, int tile_z
 // ---------------------------------------------------------------------------
 template <int TZ, bool COMP>
 __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int njobs,
-                                               uint64_t total)
+                                               uint64_t lo, uint64_t total)
 {
     using TC = TileShape<TZ, 8>;
     constexpr int IV = (TC::NV + 63) / 64;
@@ -1562,7 +1564,7 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
     // tiles from the end of the list first: those cut by the field's far
     // faces (slower, general line code) gather there and start early rather
     // than form the launch's tail
-    for (uint64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    for (uint64_t w = blockIdx.x; w < total - lo; w += gridDim.x) {
         const uint64_t u = total - 1 - w;
         const Job &J = jobs[find_job<WK_TILE>(jobs, njobs, u)];
         const FieldState *st = J.st;
@@ -1669,27 +1671,28 @@ __global__ __launch_bounds__(64) void k_coarse(const Job *__restrict__ jobs, int
 }
 
 template <int TZ>
-static void launch_coarse_t(const Job *d_jobs, int njobs, uint64_t total, bool compress,
+static void launch_coarse_t(const Job *d_jobs, int njobs, uint64_t lo, uint64_t hi, bool compress,
                             hipStream_t s)
 {
-    const uint32_t g = (uint32_t)(total < (1u << 30) ? total : (1u << 30));
+    const uint64_t n = hi - lo;
+    const uint32_t g = (uint32_t)(n < (1u << 30) ? n : (1u << 30));
     if (compress)
-        hipLaunchKernelGGL((k_coarse<TZ, true>), dim3(g), dim3(64), 0, s, d_jobs, njobs, total);
+        hipLaunchKernelGGL((k_coarse<TZ, true>), dim3(g), dim3(64), 0, s, d_jobs, njobs, lo, hi);
     else
-        hipLaunchKernelGGL((k_coarse<TZ, false>), dim3(g), dim3(64), 0, s, d_jobs, njobs, total);
+        hipLaunchKernelGGL((k_coarse<TZ, false>), dim3(g), dim3(64), 0, s, d_jobs, njobs, lo, hi);
 }
 
-void launch_coarse(const Job *d_jobs, int njobs, uint64_t total, int tile_z, bool compress,
-                   hipStream_t s)
+void launch_coarse(const Job *d_jobs, int njobs, uint64_t lo, uint64_t hi, int tile_z,
+                   bool compress, hipStream_t s)
 {
-    if (total == 0)
+    if (hi <= lo)
         return;
     if (tile_z == 1)
-        launch_coarse_t<1>(d_jobs, njobs, total, compress, s);
+        launch_coarse_t<1>(d_jobs, njobs, lo, hi, compress, s);
     else if (tile_z == 4)
-        launch_coarse_t<4>(d_jobs, njobs, total, compress, s);
+        launch_coarse_t<4>(d_jobs, njobs, lo, hi, compress, s);
     else
-        launch_coarse_t<2>(d_jobs, njobs, total, compress, s);
+        launch_coarse_t<2>(d_jobs, njobs, lo, hi, compress, s);
 }
 
 uint64_t coarse_values_per_tile(int tile_z)

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -44,9 +45,7 @@ struct Pending {
 struct GraphKey {
     int kind; // 0 compress, 1 decompress
     int njobs;
-    int tz;
-    int pad;
-    uint64_t v[12];
+    uint64_t v[24];
     const void *ws;
     const void *pinned;
 };
@@ -149,15 +148,53 @@ int ilog2(uint64_t v)
     return l;
 }
 
-// Huffman chunk length keyed by field size: enough chunks to keep every
-// decoder lane busy, never below 256 or above 1024 symbols.
-uint32_t default_chunk(uint64_t N)
+// Launch defaults of a field: Huffman chunk length and tile depth, read off
+// a table measured once on an MI355X by paper_2507_11165_amd/tune_table.py
+// (compress + decompress of one field per shape, chunk length and tile
+// depth). Each row holds a measured shape and its pick: the chunk length with
+// the highest compress + decompress throughput among those whose compression
+// ratio is within 1 % of the best ratio, and the fastest tile depth for it. A
+// field takes the row nearest to it in (log N, log dz); a tile depth above the
+// field's block count along z is lowered to it.
+struct LaunchRow {
+    uint64_t dims[3];
+    uint32_t chunk;
+    int tz;
+};
+constexpr LaunchRow kLaunchTable[] = {
+    {{64, 64, 64}, 1024, 1},     {{128, 128, 128}, 1024, 2}, {{192, 192, 192}, 1024, 4},
+    {{256, 256, 256}, 1024, 2},  {{100, 500, 500}, 1024, 2}, {{384, 384, 384}, 1024, 2},
+    {{512, 512, 512}, 1024, 2},  {{384, 96, 48}, 1024, 1},   {{48, 96, 384}, 1024, 2},
+};
+
+struct LaunchDefaults {
+    uint32_t chunk;
+    int tz;
+};
+
+LaunchDefaults default_launch(const uint64_t dims[3])
 {
-    uint64_t c = pow2ceil(cdiv(N, 131072));
-    return (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(256, c));
+    const double n = std::log2((double)dims[0] * (double)dims[1] * (double)dims[2]);
+    const double z = std::log2((double)dims[2]);
+    const LaunchRow *best = &kLaunchTable[0];
+    double bd = 1e300;
+    for (const LaunchRow &r : kLaunchTable) {
+        const double rn = std::log2((double)r.dims[0] * (double)r.dims[1] * (double)r.dims[2]);
+        const double rz = std::log2((double)r.dims[2]);
+        const double d = (n - rn) * (n - rn) + (z - rz) * (z - rz);
+        if (d < bd) {
+            bd = d;
+            best = &r;
+        }
+    }
+    LaunchDefaults L{best->chunk, best->tz};
+    const uint64_t nbz = cdiv(dims[2], kAnchor);
+    while (L.tz > 1 && (uint64_t)L.tz > nbz)
+        L.tz >>= 1;
+    return L;
 }
 
-constexpr int kDefaultTileZ = 2;
+int depth_index(int tz) { return tz == 1 ? 0 : tz == 2 ? 1 : 2; }
 
 // ---- profiling ----
 hipEvent_t take_event(hiz_ctx *c)
@@ -500,9 +537,10 @@ hiz_status check_params(const hiz_params *params, hiz_params &p, int &tz, const 
         msg = "chunk must be a power of two in [256, 65536]";
         return HIZ_ERR_ARG;
     }
-    tz = p.tile_z ? (int)p.tile_z : kDefaultTileZ;
-    if (tz != 1 && tz != 2 && tz != 4) {
-        msg = "tile_z must be 1, 2 or 4";
+    // 0: each field's tile depth from the launch table
+    tz = (int)p.tile_z;
+    if (tz != 0 && tz != 1 && tz != 2 && tz != 4) {
+        msg = "tile_z must be 0, 1, 2 or 4";
         return HIZ_ERR_ARG;
     }
     if (p.pipeline > HIZ_PIPE_CR) {
@@ -567,7 +605,10 @@ hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode,
         }
         N *= dims[k];
     }
-    const uint32_t chunk = p.chunk ? p.chunk : default_chunk(N);
+    const LaunchDefaults dl = default_launch(dims);
+    const uint32_t chunk = p.chunk ? p.chunk : dl.chunk;
+    if (!tz)
+        tz = dl.tz;
     memset(&J, 0, sizeof(J));
     J.field = d_field;
     J.stream = static_cast<uint8_t *>(d_out);
@@ -581,6 +622,7 @@ hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode,
                                                    : 0;
     }
     J.N = N;
+    J.tz = (uint8_t)tz;
     J.ntz = (uint32_t)cdiv(J.nb[2], tz);
     J.n_anchors = (uint64_t)J.nb[0] * J.nb[1] * J.nb[2];
     J.chunk = chunk;
@@ -642,6 +684,7 @@ void plan_decompress(const Parsed &P, const void *d_in, uint64_t in_size, float 
         J.nb[k] = (uint32_t)cdiv(J.dims[k], kAnchor);
     }
     J.N = P.N;
+    J.tz = (uint8_t)tz;
     J.ntz = (uint32_t)cdiv(J.nb[2], tz);
     J.n_anchors = (uint64_t)J.nb[0] * J.nb[1] * J.nb[2];
     J.chunk = P.info.chunk;
@@ -679,6 +722,9 @@ struct Totals {
     uint64_t max_n = 0;        // largest field (reordering launch)
     bool reorder = false;      // some field's codes are reordered
     uint64_t max_clear = 0;    // longest look-back array any field clears at the start
+    // per tile depth (jobs ordered by depth): jobs [jlo, jhi) with tiles [tlo, thi)
+    int jlo[kTileDepths] = {0, 0, 0}, jhi[kTileDepths] = {0, 0, 0};
+    uint64_t tlo[kTileDepths] = {0, 0, 0}, thi[kTileDepths] = {0, 0, 0};
 };
 
 // Lay out the workspace for `jobs`, set their prefixes and device pointers,
@@ -699,8 +745,9 @@ struct Sections {
 
 // Take one field's sections from the arena and add its work units to the
 // launch totals (its work-list prefixes are the totals before it).
-void take_sections(Arena &A, Job &J, bool decompress, int tz, Totals &T, Sections &o)
+void take_sections(Arena &A, Job &J, bool decompress, Totals &T, Sections &o)
 {
+    const int tz = J.tz;
     memset(&o, 0, sizeof(o));
     o.st = A.take(sizeof(FieldState));
     o.codes = A.take(J.N);
@@ -777,8 +824,52 @@ bool totals_fit(const Totals &T)
            T.tiles <= 0xffffffffull && T.lc <= 0xffffffffull && T.ou <= 0xffffffffull;
 }
 
-hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, int tz, Totals &T,
-                  Layout &L)
+// Per-depth job and tile ranges of a Job table ordered by tile depth.
+void depth_ranges(const Job *jobs, int nj, Totals &T)
+{
+    for (int d = 0; d < kTileDepths; d++) {
+        T.jlo[d] = T.jhi[d] = 0;
+        T.tlo[d] = T.thi[d] = 0;
+    }
+    int j = 0;
+    for (int d = 0; d < kTileDepths; d++) {
+        T.jlo[d] = j;
+        T.tlo[d] = j < nj ? jobs[j].tile_begin : T.tiles;
+        while (j < nj && depth_index(jobs[j].tz) == d)
+            j++;
+        T.jhi[d] = j;
+        T.thi[d] = j < nj ? jobs[j].tile_begin : T.tiles;
+    }
+}
+
+// Stable order of a call's jobs by tile depth, so that each depth's jobs and
+// tiles are contiguous (one launch of the tile kernels per depth); `field`
+// and `extra` (when not empty) follow the jobs.
+void order_by_depth(std::vector<Job> &jobs, std::vector<int> &field, std::vector<uint64_t> &extra)
+{
+    const size_t n = jobs.size();
+    std::vector<size_t> idx(n);
+    for (size_t i = 0; i < n; i++)
+        idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+        return depth_index(jobs[a].tz) < depth_index(jobs[b].tz);
+    });
+    std::vector<Job> j2(n);
+    std::vector<int> f2(n);
+    std::vector<uint64_t> e2(extra.empty() ? 0 : n);
+    for (size_t i = 0; i < n; i++) {
+        j2[i] = jobs[idx[i]];
+        f2[i] = field[idx[i]];
+        if (!extra.empty())
+            e2[i] = extra[idx[i]];
+    }
+    jobs.swap(j2);
+    field.swap(f2);
+    if (!extra.empty())
+        extra.swap(e2);
+}
+
+hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, Totals &T, Layout &L)
 {
     const int nj = (int)jobs.size();
     Arena A;
@@ -788,7 +879,8 @@ hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, int tz, T
     std::vector<Sections> o(nj);
     T = Totals();
     for (int j = 0; j < nj; j++)
-        take_sections(A, jobs[j], decompress, tz, T, o[j]);
+        take_sections(A, jobs[j], decompress, T, o[j]);
+    depth_ranges(jobs.data(), nj, T);
     if (!totals_fit(T))
         return fail(c, HIZ_ERR_ARG, "batch too large for one launch");
     hiz_status rc = ensure_ws(c, A.off);
@@ -812,8 +904,15 @@ hiz_status layout(hiz_ctx *c, std::vector<Job> &jobs, bool decompress, int tz, T
 
 // The launch sequence of compression (Sec. 5: range and bound, tuner,
 // interpolation + quantization + histogram, codebook, encoding) for all jobs.
-void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int tz,
-                      hipStream_t s, bool prof)
+// Claim counters of the tile kernels of one depth (a device address).
+uint32_t *depth_counters(const Layout &L, int d)
+{
+    return reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(L.d_cnt) +
+                                        offsetof(Counters, tile_next)) + 8 * d;
+}
+
+void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, hipStream_t s,
+                      bool prof)
 {
     hipMemcpyAsync(L.d_jobs, L.h_jobs, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
     {
@@ -836,14 +935,23 @@ void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int 
         Scope sc(c, s, "tune_pick", prof);
         launch_tune_pick(L.d_jobs, nj, s);
     }
-    {
-        Scope sc(c, s, "coarse", prof);
-        launch_coarse(L.d_jobs, nj, T.tiles, tz, true, s);
-    }
-    {
-        Scope sc(c, s, "predict_quant", prof);
-        launch_predict(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, false), L.d_cnt,
-                       s);
+    // the tile kernels: one launch per tile depth present
+    for (int d = 0; d < kTileDepths; d++) {
+        if (T.thi[d] <= T.tlo[d])
+            continue;
+        const int tz = 1 << d;
+        const Job *dj = L.d_jobs + T.jlo[d];
+        const int nd = T.jhi[d] - T.jlo[d];
+        {
+            Scope sc(c, s, "coarse", prof);
+            launch_coarse(dj, nd, T.tlo[d], T.thi[d], tz, true, s);
+        }
+        {
+            Scope sc(c, s, "predict_quant", prof);
+            launch_predict(dj, nd, T.tlo[d], T.thi[d], tz,
+                           predict_grid(c, tz, T.thi[d] - T.tlo[d], false), depth_counters(L, d),
+                           s);
+        }
     }
     if (T.reorder) {
         Scope sc(c, s, "reorder", prof);
@@ -870,8 +978,8 @@ void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int 
 }
 
 // The launch sequence of decompression (decode, outliers, reconstruction).
-void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, int tz,
-                        hipStream_t s, bool prof)
+void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, hipStream_t s,
+                        bool prof)
 {
     hipMemcpyAsync(L.d_jobs, L.h_jobs, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
     {
@@ -898,14 +1006,22 @@ void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, in
         Scope sc(c, s, "scatter", prof);
         launch_scatter(L.d_jobs, nj, T.out, s);
     }
-    {
-        Scope sc(c, s, "coarse_rec", prof);
-        launch_coarse(L.d_jobs, nj, T.tiles, tz, false, s);
-    }
-    {
-        Scope sc(c, s, "reconstruct", prof);
-        launch_reconstruct(L.d_jobs, nj, T.tiles, tz, predict_grid(c, tz, T.tiles, true),
-                           L.d_cnt, s);
+    for (int d = 0; d < kTileDepths; d++) {
+        if (T.thi[d] <= T.tlo[d])
+            continue;
+        const int tz = 1 << d;
+        const Job *dj = L.d_jobs + T.jlo[d];
+        const int nd = T.jhi[d] - T.jlo[d];
+        {
+            Scope sc(c, s, "coarse_rec", prof);
+            launch_coarse(dj, nd, T.tlo[d], T.thi[d], tz, false, s);
+        }
+        {
+            Scope sc(c, s, "reconstruct", prof);
+            launch_reconstruct(dj, nd, T.tlo[d], T.thi[d], tz,
+                               predict_grid(c, tz, T.thi[d] - T.tlo[d], true),
+                               depth_counters(L, d), s);
+        }
     }
     launch_gather_results(L.d_jobs, nj, L.d_res, s);
     hipMemcpyAsync(L.h_res, L.d_res, (size_t)kResultBytes * nj, hipMemcpyDeviceToHost, s);
@@ -914,14 +1030,14 @@ void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, in
 // Run the sequence eagerly, or replay (building on first use) the HIP graph of
 // this launch geometry. Graph replay re-reads the Job table from the same
 // pinned buffer, so only the geometry has to match.
-hiz_status enqueue(hiz_ctx *c, int kind, const Layout &L, int nj, const Totals &T, int tz,
+hiz_status enqueue(hiz_ctx *c, int kind, const Layout &L, int nj, const Totals &T,
                    hipStream_t s)
 {
     if (!c->graphs) {
         if (kind == 0)
-            enqueue_compress(c, L, nj, T, tz, s, true);
+            enqueue_compress(c, L, nj, T, s, true);
         else
-            enqueue_decompress(c, L, nj, T, tz, s, true);
+            enqueue_decompress(c, L, nj, T, s, true);
         HIP_TRY(c, hipGetLastError());
         return HIZ_OK;
     }
@@ -929,15 +1045,17 @@ hiz_status enqueue(hiz_ctx *c, int kind, const Layout &L, int nj, const Totals &
     memset(&key, 0, sizeof(key));
     key.kind = kind;
     key.njobs = nj;
-    key.tz = tz;
-    const uint64_t v[12] = {T.mm,       T.tune,  T.tiles, T.chunks,
-                            T.groups,   T.dblk,  T.out,   T.max_groups,
-                            T.max_dblk, (uint64_t)c->cus, T.lc, T.ou};
+    const uint64_t v[24] = {T.mm,       T.tune,    T.tiles,    T.chunks,  T.groups, T.dblk,
+                            T.out,      T.max_groups, T.max_dblk, (uint64_t)c->cus, T.lc, T.ou,
+                            (uint64_t)T.jlo[0], (uint64_t)T.jlo[1], (uint64_t)T.jlo[2],
+                            (uint64_t)T.jhi[0], (uint64_t)T.jhi[1], (uint64_t)T.jhi[2],
+                            T.tlo[0],   T.tlo[1],  T.tlo[2],   T.thi[0],  T.thi[1], T.thi[2]};
     memcpy(key.v, v, sizeof(v));
     key.ws = c->ws;
     key.pinned = c->pinned;
     // occupancy queries stay outside the capture
-    predict_grid(c, tz, 1, kind == 1);
+    for (int tz = 1; tz <= 4; tz *= 2)
+        predict_grid(c, tz, 1, kind == 1);
     encode_grid(c);
     GraphSlot *hit = nullptr;
     for (GraphSlot &g : c->gslot)
@@ -956,9 +1074,9 @@ hiz_status enqueue(hiz_ctx *c, int kind, const Layout &L, int nj, const Totals &
         }
         HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         if (kind == 0)
-            enqueue_compress(c, L, nj, T, tz, c->cap_stream, false);
+            enqueue_compress(c, L, nj, T, c->cap_stream, false);
         else
-            enqueue_decompress(c, L, nj, T, tz, c->cap_stream, false);
+            enqueue_decompress(c, L, nj, T, c->cap_stream, false);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess || !g) {
@@ -1058,13 +1176,15 @@ hiz_status submit_compress(hiz_ctx *c, int n, const float *const *d_fields, cons
     }
     B.njobs = (int)jobs.size();
     if (B.njobs) {
+        std::vector<uint64_t> none;
+        order_by_depth(jobs, B.field, none);
         Totals T;
         Layout L;
-        rc = layout(c, jobs, false, tz, T, L);
+        rc = layout(c, jobs, false, T, L);
         if (rc)
             return abandon(c, s, rc);
         B.h_res = L.h_res;
-        rc = enqueue(c, 0, L, B.njobs, T, tz, s);
+        rc = enqueue(c, 0, L, B.njobs, T, s);
         if (rc)
             return abandon(c, s, rc);
     }
@@ -1090,7 +1210,6 @@ hiz_status submit_decompress(hiz_ctx *c, int n, const void *const *d_ins,
     HIP_TRY(c, hipSetDevice(c->device));
     begin_batch(c, 1, n, s);
     Batch &B = c->batch;
-    const int tz = kDefaultTileZ;
     // headers and code-length tables of every stream, in one synchronization
     hiz_status rc = ensure_pinned(c, (uint64_t)kOffChunks * std::max(n, 1));
     if (rc)
@@ -1155,7 +1274,8 @@ hiz_status submit_decompress(hiz_ctx *c, int n, const void *const *d_ins,
         if (B.status[i] || P[i].info.constant)
             continue;
         Job J;
-        plan_decompress(P[i], d_ins[i], in_sizes[i], d_fields[i], tz, J);
+        plan_decompress(P[i], d_ins[i], in_sizes[i], d_fields[i],
+                        default_launch(P[i].info.dims).tz, J);
         jobs.push_back(J);
         B.field.push_back(i);
         B.n_out.push_back(J.n_out);
@@ -1164,13 +1284,14 @@ hiz_status submit_decompress(hiz_ctx *c, int n, const void *const *d_ins,
         return abandon(c, s, fail(c, HIZ_ERR_HIP, "fill launch failed"));
     B.njobs = (int)jobs.size();
     if (B.njobs) {
+        order_by_depth(jobs, B.field, B.n_out);
         Totals T;
         Layout L;
-        rc = layout(c, jobs, true, tz, T, L);
+        rc = layout(c, jobs, true, T, L);
         if (rc)
             return abandon(c, s, rc);
         B.h_res = L.h_res;
-        rc = enqueue(c, 1, L, B.njobs, T, tz, s);
+        rc = enqueue(c, 1, L, B.njobs, T, s);
         if (rc)
             return abandon(c, s, rc);
     }
@@ -1301,7 +1422,8 @@ hiz_status compress_noalloc(hiz_ctx *c, const float *d_field, const uint64_t dim
     const uint64_t o_res = A.take(kResultBytes);
     Totals T;
     Sections o;
-    take_sections(A, J, false, tz, T, o);
+    take_sections(A, J, false, T, o);
+    depth_ranges(&J, 1, T);
     if (!totals_fit(T))
         return fail(c, HIZ_ERR_ARG, "field too large for one launch");
     if (A.off > kScratchBytes)
@@ -1320,7 +1442,7 @@ hiz_status compress_noalloc(hiz_ctx *c, const float *d_field, const uint64_t dim
     L.d_res = c->scratch + o_res;
     L.h_res = c->pinned + job_bytes;
     L.h_jobs = c->pinned;
-    enqueue_compress(c, L, 1, T, tz, s, false);
+    enqueue_compress(c, L, 1, T, s, false);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(s));
     FieldState res;

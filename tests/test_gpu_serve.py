@@ -56,7 +56,9 @@ def test_served_results_equal_single_calls(hz):
     caps = [hz.compress_bound(x.shape) for x in xs]
     outs = [torch.empty(c, dtype=torch.uint8, device=DEV) for c in caps]
     torch.cuda.synchronize()
-    srv = hz.Server(0, slots=3, mem_budget=1 << 30, max_batch=8)
+    # an explicit chunk length, so that the oracle below takes the same one
+    params = hz.make_params(tune=True, chunk=256)
+    srv = hz.Server(0, slots=3, mem_budget=1 << 30, max_batch=8, params=params)
     _say(f"serving {len(xs)} compress requests")
     # bursts: some requests arrive while others run
     for i, x in enumerate(xs):
@@ -74,7 +76,7 @@ def test_served_results_equal_single_calls(hz):
     for i, x in enumerate(xs):
         c = got[i]
         assert c["status"] == 0, (i, c)
-        single = ctx.compress(fields[i], "rel", ebs[i]).cpu().numpy()
+        single = ctx.compress(fields[i], "rel", ebs[i], params).cpu().numpy()
         served = outs[i][:c["size"]].cpu().numpy()
         assert np.array_equal(served, single), f"request {i} {x.shape} differs from a single call"
         assert c["t_submit"] <= c["t_start"] <= c["t_done"]
@@ -90,8 +92,7 @@ def test_served_results_equal_single_calls(hz):
         assert got[1000 + i]["status"] == 0
         alone = ctx.decompress(outs[i][:sizes[i]]).cpu().numpy()
         assert np.array_equal(ys[i].cpu().numpy().view(np.uint32), alone.view(np.uint32)), i
-    # the smallest few against the oracle (fields this small get the shortest
-    # default Huffman chunk, 256 symbols)
+    # the smallest few against the oracle, at the same chunk length
     for i in sorted(range(len(xs)), key=lambda k: xs[k].size)[:3]:
         ref = O.compress(xs[i], O.REL, ebs[i], tune=True, cfg=O.DEFAULT_CFG, chunk=256,
                          debug=False)
