@@ -49,11 +49,18 @@ enum : uint32_t {
 
 // Decoder lookup tables of one field, built once per decompression.
 constexpr int kLutBits = 13;
+// Decoder lookup entry for the next kLutBits payload bits: the one or two
+// whole codes that fit in them. Bits 0..4: 32 - (their total length); bits
+// 5..6: how many (1 or 2); bits 8..15, 16..23: the symbols in order; bits
+// 24..28: the length of the first code. 0: the first code is longer than
+// kLutBits bits (its length comes from `limit`).
 struct DecTables {
-    uint16_t lut[1 << kLutBits]; // (symbol << 8) | (32 - len) for codes up to kLutBits bits; 0 = slow path
+    uint32_t lut[1 << kLutBits];
     uint32_t first[kMaxCodeLen + 2]; // first canonical code of each length
     uint32_t count[kMaxCodeLen + 2]; // codes of each length
     uint32_t index[kMaxCodeLen + 2]; // position of the first code of each length in `sorted`
+    uint32_t limit[kMaxCodeLen + 2]; // first left-justified 32-bit window past the codes of each length
+    uint32_t base[kMaxCodeLen + 2];  // index - first (mod 2^32): sorted[base[L] + code]
     uint8_t sorted[256];             // symbols by (length, symbol)
     uint32_t maxlen;
     uint32_t pad[3];

@@ -5,6 +5,8 @@
 // decompression.
 #include "hiz_internal.h"
 
+#include <type_traits>
+
 namespace hiz {
 
 template <typename T> __device__ inline void put_le(uint8_t *p, T v)
@@ -346,8 +348,19 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
     const uint64_t g = gid - J.group_begin;
     const uint64_t cfirst = g * kGroupChunks;
     const int nc = (int)min<uint64_t>(kGroupChunks, J.n_chunks - cfirst);
-    for (int k = 0; k < kGroupChunks / kEncWaves; k++) {
-        const int lc = wv * (kGroupChunks / kEncWaves) + k;
+    // chunks of exactly one segment (kEncSeg codes, 16 per lane): the next
+    // chunk's codes are loaded while this one is sized
+    const bool seg1 = J.chunk == (uint32_t)kEncSeg;
+    const int kw = kGroupChunks / kEncWaves;
+    HIZ_GLOBAL const uint8_t *seq = gmem(J.seq);
+    uint4 nxt = make_uint4(0u, 0u, 0u, 0u);
+    auto full_chunk = [&](int lc) {
+        return lc < nc && ((cfirst + lc + 1) << J.log2_chunk) <= J.N;
+    };
+    if (seg1 && full_chunk(wv * kw))
+        nxt = gload_u4(seq + ((cfirst + wv * kw) << J.log2_chunk) + 16 * lane);
+    for (int k = 0; k < kw; k++) {
+        const int lc = wv * kw + k;
         if (lc >= nc)
             break;
         const uint64_t ck = cfirst + lc;
@@ -355,15 +368,24 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
         const int clen = (int)(min(c0 + J.chunk, J.N) - c0);
         uint64_t bits = 0;
         uint32_t zeros = 0;
-        for (int sg = 0; sg * kEncSeg < clen; sg++) {
-            const int sl = min(kEncSeg, clen - sg * kEncSeg);
-            const int P = (sl + 63) / 64;
-            const int n = max(0, min(P, sl - lane * P));
-            uint32_t r[4], b, z;
-            load_lane_codes(gmem(J.seq) + c0 + sg * kEncSeg + lane * P, P, n, r);
-            lane_sizes(r, n, len, b, z);
-            bits += b;
-            zeros += z;
+        if (seg1 && clen == kEncSeg) {
+            uint32_t r[4] = {nxt.x, nxt.y, nxt.z, nxt.w}, b, z;
+            if (k + 1 < kw && full_chunk(lc + 1))
+                nxt = gload_u4(seq + ((ck + 1) << J.log2_chunk) + 16 * lane);
+            lane_sizes(r, 16, len, b, z);
+            bits = b;
+            zeros = z;
+        } else {
+            for (int sg = 0; sg * kEncSeg < clen; sg++) {
+                const int sl = min(kEncSeg, clen - sg * kEncSeg);
+                const int P = (sl + 63) / 64;
+                const int n = max(0, min(P, sl - lane * P));
+                uint32_t r[4], b, z;
+                load_lane_codes(seq + c0 + sg * kEncSeg + lane * P, P, n, r);
+                lane_sizes(r, n, len, b, z);
+                bits += b;
+                zeros += z;
+            }
         }
         for (int o = 32; o > 0; o >>= 1) {
             bits += shfl64(bits, lane ^ o);
@@ -610,9 +632,9 @@ void launch_init_decompress(const Job *d_jobs, int njobs, uint64_t max_blocks, C
 }
 
 // Decoder tables from the stored code lengths: canonical codes, a direct
-// lookup table for codes up to kLutBits bits and per-length ranges for the
-// longer ones. The lookup table is built by kDecTableParts workgroups per
-// field, one slice each; the first also writes the per-length tables.
+// lookup table of up to two codes within kLutBits bits, and per-length ranges
+// for longer codes. The lookup table is built by kDecTableParts workgroups
+// per field, one slice each; the first also writes the per-length tables.
 constexpr int kDecTableParts = 8;
 
 __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs, int njobs)
@@ -653,6 +675,11 @@ __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs
         dt->first[t] = first[t];
         dt->count[t] = blc[t];
         dt->index[t] = index[t];
+        dt->base[t] = index[t] - first[t];
+        // the codes of length t end where those of length t + 1 start,
+        // left-justified: (first + count) << (32 - t), saturated
+        const uint64_t end = t >= 1 ? ((uint64_t)first[t] + blc[t]) << (32 - t) : 0;
+        dt->limit[t] = end > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)end;
     }
     if (L >= 1 && L <= kMaxCodeLen) {
         uint32_t k = 0;
@@ -663,19 +690,30 @@ __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs
     __syncthreads();
     if (blockIdx.x == 0)
         dt->sorted[t] = s_sorted[t];
-    // this part's table entries, each by itself: the shortest code that
-    // prefixes its index
+    // this part's table entries, each by itself: the first code that
+    // prefixes its index, then a second one if it fits in the rest
     constexpr uint32_t kPart = (1u << kLutBits) / kDecTableParts;
     for (uint32_t e = blockIdx.x * kPart + t; e < (blockIdx.x + 1) * kPart; e += 256) {
-        uint16_t v = 0;
-        for (int b = 1; b <= kLutBits; b++) {
-            const uint32_t c = e >> (kLutBits - b);
-            if (blc[b] && c - first[b] < blc[b]) {
-                v = (uint16_t)(((uint32_t)s_sorted[index[b] + (c - first[b])] << 8) | (32u - b));
-                break;
+        uint32_t used = 0, n = 0, syms = 0, l1 = 0;
+        while (n < 2) {
+            uint32_t Lc = 0, sym = 0;
+            for (uint32_t b = 1; b + used <= (uint32_t)kLutBits; b++) {
+                const uint32_t c = (e >> (kLutBits - used - b)) & ((1u << b) - 1u);
+                if (blc[b] && c - first[b] < blc[b]) {
+                    Lc = b;
+                    sym = s_sorted[index[b] + (c - first[b])];
+                    break;
+                }
             }
+            if (!Lc)
+                break;
+            if (n == 0)
+                l1 = Lc;
+            syms |= sym << (8 * n);
+            n++;
+            used += Lc;
         }
-        dt->lut[e] = v;
+        dt->lut[e] = n ? ((32u - used) | (n << 5) | (syms << 8) | (l1 << 24)) : 0u;
     }
 }
 
@@ -686,20 +724,23 @@ void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s)
 
 // One thread per chunk; a workgroup takes 256 consecutive chunks, finds its
 // payload offset by look-back over the stored word counts, and each thread
-// decodes its chunk sequentially with the LDS lookup table.
+// decodes its chunk sequentially with the LDS lookup table, up to three
+// codes per table read.
 constexpr int kDecChunks = 256;
-constexpr int kRing = 32; // payload words of a decoder lane's LDS ring (a power of two)
+constexpr int kRing = 32;      // payload words of a decoder lane's LDS ring (a power of two)
+constexpr int kRowBytes = 36;  // a lane's LDS output ring: 32 codes, padding (odd in words)
 
 __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, int njobs,
                                                 uint64_t total, Counters *cnt)
 {
-    __shared__ uint16_t lut[1 << kLutBits];
-    __shared__ uint32_t first[kMaxCodeLen + 2], count[kMaxCodeLen + 2], index[kMaxCodeLen + 2];
+    __shared__ __align__(16) uint32_t lut[1 << kLutBits];
+    __shared__ uint32_t limit[kMaxCodeLen + 2], base[kMaxCodeLen + 2];
     __shared__ uint8_t sorted[256];
     __shared__ uint32_t s_id, s_maxlen;
     __shared__ uint64_t s_wsum[4];
     __shared__ uint64_t s_base;
     __shared__ uint32_t s_win[kDecChunks * kRing];
+    __shared__ __align__(16) uint8_t s_rows[kDecChunks * kRowBytes];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (t == 0)
         s_id = atomicAdd(&cnt->dec_next, 1u);
@@ -709,12 +750,15 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         return;
     const Job &J = jobs[find_job<WK_DBLK>(jobs, njobs, id)];
     const DecTables *dt = J.dt;
-    for (int i = t; i < (1 << kLutBits); i += 256)
-        lut[i] = dt->lut[i];
+    {
+        HIZ_GLOBAL const uint8_t *src = reinterpret_cast<HIZ_GLOBAL const uint8_t *>(gmem(dt->lut));
+        uint4 *dst = reinterpret_cast<uint4 *>(lut);
+        for (int i = t; i < (1 << kLutBits) / 4; i += 256)
+            dst[i] = gload_u4(src + 16 * i);
+    }
     if (t <= kMaxCodeLen) {
-        first[t] = dt->first[t];
-        count[t] = dt->count[t];
-        index[t] = dt->index[t];
+        limit[t] = dt->limit[t];
+        base[t] = dt->base[t];
     }
     sorted[t] = dt->sorted[t];
     if (t == 0)
@@ -765,17 +809,19 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     const uint32_t maxlen = s_maxlen;
     const uint64_t wend = start + wc;
     // Payload words reach the decoder through a per-lane ring of kRing words in
-    // LDS. Symbols are decoded in blocks of 16, the same for every lane of the
-    // wave; at each block boundary the words prefetched during the previous
-    // block are committed to the ring and, if the ring has room, the next 16
-    // are requested. A block consumes at most 16 words (codewords are at most
-    // 32 bits), so the ring holding 16 words at a block's start is enough; a
+    // LDS. Symbols are decoded in rounds of 16, the same for every lane of the
+    // wave; at each round boundary the words prefetched during the previous
+    // round are committed to the ring and, if the ring has room, the next 16
+    // are requested. A round consumes at most 16 words (codewords are at most
+    // 32 bits), so the ring holding 16 words at a round's start is enough; a
     // lane below that (codes far longer than usual) refills synchronously.
-    // Words past the chunk's end read as zero.
-    // slot i of this lane's ring is s_win[i * kDecChunks + t]: the lanes of
-    // a wave touch consecutive words whatever slots they are at (no bank
-    // conflicts)
+    // Words past the chunk's end read as zero. Slot i of this lane's ring is
+    // s_win[i * kDecChunks + t]: the lanes of a wave touch consecutive words
+    // whatever slots they are at (no bank conflicts).
     uint32_t *ring = s_win + t;
+    // this lane's 32-byte output ring; the stride is odd in words, so lanes
+    // at the same position write different banks
+    uint8_t *row = s_rows + t * kRowBytes;
     // payload word idx of this chunk, 0 past its end; the load itself is never
     // skipped (its index is clamped inside the payload), so a run of them is
     // issued back to back without a branch or a wait between them
@@ -798,22 +844,105 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         wfetch += 16;
     }
     wp = 32;
-    uint64_t used = 0;
     uint32_t zeros = 0;
     bool bad = false;
-    // Bit buffer: the next nb (33..64 before a symbol) payload bits, first
-    // bit at the top of hi, then lo; zeros below them. idx is the table index
-    // of the next code (its first kLutBits bits). The word after the buffer
+    // Ends of the code ranges of the lengths past the table (kLutBits + 1 ..
+    // maxlen - 1), left-justified, less one (all ones for the lengths not
+    // used): the same for every lane, kept in scalar registers. A code
+    // longer than the table has length kLutBits + 1 plus the number of these
+    // its window is above.
+    uint32_t lim[kMaxCodeLen - kLutBits - 1];
+#pragma unroll
+    for (int k = 0; k < kMaxCodeLen - kLutBits - 1; k++) {
+        const int Lk = kLutBits + 1 + k;
+        lim[k] = __builtin_amdgcn_readfirstlane((uint32_t)Lk < maxlen ? limit[Lk] - 1u : 0xFFFFFFFFu);
+    }
+    // Bit buffer: the next nb (32..63 before a step) payload bits, first bit
+    // at the top of hi, then lo; zeros below them. The word after the buffer
     // waits in nextw, so a refill never waits for LDS; rp counts words taken
-    // out of the ring.
+    // out of the ring. e is the table entry of the buffer's first kLutBits
+    // bits, read a step ahead.
     uint32_t hi = ring[0], lo = ring[kDecChunks], nextw = ring[2 * kDecChunks];
     rp = 3;
     int nb = 64;
     uint32_t e = lut[hi >> (32 - kLutBits)];
-    const uint32_t nblk = (nsym + 15) >> 4;
+    uint32_t pos = 0, flushed = 0; // codes decoded (padding past the end included) / stored
+    uint32_t cb = 0, ub = 0;       // tail rounds: bits taken so far / by the chunk's own codes
+    bool tail = false;             // the same for the whole wave
+    // One step: the one or two codes of entry e. It shifts the buffer by
+    // their length, reads the next entry straight from the shifted buffer (an
+    // entry takes at most kLutBits of the 32 or more valid bits), writes the
+    // two symbol bytes at the lane's output position (a second byte past the
+    // entry's count is overwritten later) and advances by the count, then
+    // refills by masks when fewer than 32 bits remain. A code longer than the
+    // table takes its length from the range ends and its symbol from the
+    // sorted table, and the next entry is read again once the buffer is
+    // refilled. Past the chunk's last code the steps decode padding; in the
+    // tail rounds ub keeps the bits the chunk's own codes took.
+    auto step = [&](auto tail_tag) {
+        constexpr bool TAIL = decltype(tail_tag)::value;
+        const uint32_t nw = ring[(rp & (kRing - 1)) * kDecChunks];
+        const bool slow = e == 0u;
+        if (__builtin_expect(__any(slow), 0) && slow) {
+            uint32_t L = kLutBits + 1;
+#pragma unroll
+            for (int k = 0; k < kMaxCodeLen - kLutBits - 1; k++)
+                L += hi > lim[k] ? 1u : 0u;
+            uint32_t sym = 0;
+            if (L > maxlen) {
+                bad = true;
+                L = 1;
+            } else {
+                sym = sorted[(base[L] + (hi >> (32 - L))) & 255u];
+            }
+            if (L == 32) {
+                // the entry can shift by at most 31: take one bit here
+                hi = __builtin_amdgcn_alignbit(hi, lo, 31u);
+                lo <<= 1;
+                nb -= 1;
+                if (TAIL)
+                    cb += 1;
+                L = 31;
+            }
+            e = (32u - L) | (1u << 5) | (sym << 8) | (L << 24);
+        }
+        const uint32_t tb = (0u - e) & 31u; // bits the entry's codes take
+        hi = __builtin_amdgcn_alignbit(hi, lo, e);
+        lo <<= tb;
+        nb -= (int)tb;
+        uint32_t en = lut[hi >> (32 - kLutBits)];
+        row[pos & 31] = (uint8_t)(e >> 8);
+        row[(pos + 1) & 31] = (uint8_t)(e >> 16);
+        const uint32_t n = (e >> 5) & 3u;
+        if (TAIL) {
+            // a second code past the chunk's end is padding: only the first counts
+            ub = pos < nsym ? cb + ((pos + n > nsym) ? (e >> 24) : tb) : ub;
+            cb += tb;
+        }
+        pos += n;
+        // refill: m is all ones when fewer than 32 bits remain
+        const uint32_t m = (uint32_t)((nb - 32) >> 31);
+        hi |= (nextw >> nb) & m;
+        lo = (__builtin_amdgcn_alignbit(nextw, 0u, (uint32_t)nb) & m) | (lo & ~m);
+        nb += (int)(m & 32u);
+        nextw = (nw & m) | (nextw & ~m);
+        rp -= m;
+        if (__builtin_expect(__any(slow), 0) && slow)
+            en = reinterpret_cast<volatile const uint32_t *>(lut)[hi >> (32 - kLutBits)];
+        e = en;
+    };
+    auto zbytes = [](uint32_t w, uint32_t valid) -> uint32_t {
+        // 0x80 in each byte of w that is zero, then only the valid bytes
+        const uint32_t z = ~(((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w | 0x7F7F7F7Fu);
+        const uint32_t msk = valid >= 4 ? 0xFFFFFFFFu : ((1u << (8 * valid)) - 1u);
+        return (uint32_t)__builtin_popcount(z & msk);
+    };
+    // Rounds of 8 steps, the same for every lane of the wave, until every
+    // lane has stored its chunk. A round decodes at most 16 codes and takes
+    // at most 8 payload words.
 #pragma nounroll
-    for (uint32_t blk = 0; blk < nblk; blk++) {
-        // words requested a block ago enter the ring
+    while (__any(flushed < nsym)) {
+        // words requested a round ago enter the ring
         if (pending) {
 #pragma unroll
             for (int j = 0; j < 16; j++)
@@ -835,7 +964,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         }
         // request the next 16 words: decided per lane, but when any lane of
         // the wave asks every lane loads (a uniform branch keeps the loads
-        // in flight until the next block commits them)
+        // in flight until the next round commits them)
         const bool want = wp - rp <= kRing - 16;
         if (__any(want)) {
             // raw words: the words past the chunk's end are zeroed when they
@@ -848,91 +977,42 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
                 wfetch += 16;
             pending = want;
         }
-        uint32_t out[4] = {0u, 0u, 0u, 0u};
-        const uint32_t nk = min(16u, nsym - (blk << 4));
-        // one symbol. After a code is taken off the buffer, nb <= 32 asks for
-        // the next word: it goes in below the valid bits by selects (the ring
-        // word after nextw is read every time), no branch. A table hit (codes
-        // up to kLutBits bits) leaves at least 20 valid bits, so the next
-        // index comes from the shifted buffer before the refill, and the
-        // chain from one table read to the next is three operations. Longer
-        // codes take the search by length, then refill, then index.
-        auto refill = [&](uint32_t nw) {
-            const bool need = nb <= 32;
-            const uint64_t add = ((uint64_t)nextw << 32) >> (need ? nb : 0);
-            hi |= need ? (uint32_t)(add >> 32) : 0u;
-            lo |= need ? (uint32_t)add : 0u;
-            nb += need ? 32 : 0;
-            nextw = need ? nw : nextw;
-            rp += need ? 1u : 0u;
-        };
-        auto step = [&](int k, bool active) {
-            if (!active)
-                return;
-            // e, the table entry of the code at the buffer's top, was read a
-            // step ahead: (symbol << 8) | (32 - length), 0 for a longer code
-            const uint32_t nw = ring[(rp & (kRing - 1)) * kDecChunks];
-            const uint32_t hi0 = hi, lo0 = lo, nextw0 = nextw, rp0 = rp;
-            const int nb0 = nb;
-            const uint32_t sh = e & 255u;
-            uint32_t L = 32 - sh, sym = e >> 8;
-            const uint32_t nhi = __builtin_amdgcn_alignbit(hi, lo, sh);
-            // the next entry, before anything else: a table hit leaves at
-            // least 20 valid bits, so the refill below cannot change it
-            uint32_t en = lut[nhi >> (32 - kLutBits)];
-            hi = nhi;
-            lo <<= (L & 31u);
-            nb -= (int)L;
-            refill(nw);
-            // a code longer than the table (rare): search by length from the
-            // saved state, then refill and read the next entry again; the
-            // wave-uniform test keeps the common path free of exec masking
-            // and the volatile read keeps the two entry reads apart
-            if (__builtin_expect(__any(e == 0), 0) && e == 0) {
-                uint64_t b64 = ((uint64_t)hi0 << 32) | lo0;
-                sym = 0;
-                for (L = kLutBits + 1; L <= maxlen; L++) {
-                    const uint32_t c = (uint32_t)(b64 >> (64 - L));
-                    if (c - first[L] < count[L]) {
-                        sym = sorted[index[L] + (c - first[L])];
-                        break;
-                    }
-                }
-                if (L > maxlen) {
-                    bad = true;
-                    L = 1;
-                }
-                b64 <<= L;
-                hi = (uint32_t)(b64 >> 32);
-                lo = (uint32_t)b64;
-                nb = nb0 - (int)L;
-                nextw = nextw0;
-                rp = rp0;
-                refill(nw);
-                en = reinterpret_cast<volatile const uint16_t *>(lut)[hi >> (32 - kLutBits)];
-            }
-            e = en;
-            used += L;
-            zeros += (sym == 0);
-            out[k >> 2] |= sym << (8 * (k & 3));
-        };
-        if (nk == 16) {
-#pragma unroll
-            for (int k = 0; k < 16; k++)
-                step(k, true);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 16; k++)
-                step(k, (uint32_t)k < nk);
+        // tail rounds from the first round in which some lane may reach its end
+        if (!tail && __any(pos + 16 >= nsym)) {
+            tail = true;
+            cb = 32u * (rp - 1) - (uint32_t)nb;
         }
-        const uint64_t o = i0 + ((uint64_t)blk << 4);
-        if (nk == 16) {
-            gstore_u4(codes + o, make_uint4(out[0], out[1], out[2], out[3]));
+        if (tail) {
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                step(std::true_type{});
         } else {
-            for (uint32_t k = 0; k < nk; k++)
-                codes[o + k] = (uint8_t)(out[k >> 2] >> (8 * (k & 3)));
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                step(std::false_type{});
+        }
+        // a lane holding 16 codes, or its chunk's last ones, stores them from
+        // its 32-byte output ring; code-0 bytes are counted on the way
+        if (flushed < nsym && (pos >= flushed + 16 || pos >= nsym)) {
+            const uint32_t *rw = reinterpret_cast<const uint32_t *>(row + (flushed & 16));
+            const uint32_t w0 = rw[0], w1 = rw[1], w2 = rw[2], w3 = rw[3];
+            const uint32_t cnt = min(16u, nsym - flushed);
+            const uint64_t o = i0 + flushed;
+            if (cnt == 16) {
+                gstore_u4(codes + o, make_uint4(w0, w1, w2, w3));
+                zeros += zbytes(w0, 4) + zbytes(w1, 4) + zbytes(w2, 4) + zbytes(w3, 4);
+            } else {
+                const uint8_t *rb = row + (flushed & 16);
+                for (uint32_t k = 0; k < cnt; k++)
+                    codes[o + k] = rb[k];
+                zeros += zbytes(w0, cnt) + zbytes(w1, cnt > 4 ? cnt - 4 : 0) +
+                         zbytes(w2, cnt > 8 ? cnt - 8 : 0) + zbytes(w3, cnt > 12 ? cnt - 12 : 0);
+            }
+            flushed += 16;
         }
     }
+    // bits taken by the chunk's codes
+    const uint64_t used = tail ? (uint64_t)ub : 32ull * (rp - 1) - (uint64_t)nb;
     if (bad || (used + 31) / 32 != wc)
         atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
     if (zeros)
