@@ -19,6 +19,8 @@ to one host core, median of 3) on a bounded slab of the same field.
 After the headline line's measurements, the default run also measures, as
 extra keys of the same JSON line:
   eb_sweep  the same field at rel eb 1e-2 and 1e-4;
+  pipelines the same field at rel eb 1e-3 through the throughput mode
+            (TCMS1-BIT1-RRE1) and the ratio mode (Huffman + RRE4-TCMS8-RZE1);
   front     the anisotropic 100x500x500 field with a tanh front at rel eb 1e-3
             and 1e-4, with the tuner's per-level picks;
   batch64   64 uneven fields (sides 32..384, spectra k^-2..k^-4, rel eb 1e-3):
@@ -385,6 +387,18 @@ def main():
                                profile=False)
             sweep[f"{eb:g}"] = field_summary(x, me)
         res["eb_sweep"] = sweep
+        # the lossless pipelines beyond Huffman (Sec. 5.2.3) on the same field at rel 1e-3:
+        # throughput mode (TCMS1-BIT1-RRE1 on the codes) and ratio mode (Huffman, then
+        # RRE4-TCMS8-RZE1, codes reordered by level)
+        pipes = {}
+        for name, pipe in (("throughput_TCMS1-BIT1-RRE1", hiz.PIPE_TP),
+                           ("ratio_HF-RRE4-TCMS8-RZE1", hiz.PIPE_CR)):
+            log(f"pipeline: {name}")
+            pp = hiz.make_params(tune=True, chunk=args.chunk, tile_z=args.tile_z, pipeline=pipe)
+            me = measure_field(ctx, hiz, torch, xd, x, args.eb, pp, 5, 2, zbuf, ybuf, sh,
+                               profile=False)
+            pipes[name] = field_summary(x, me)
+        res["pipelines"] = pipes
         del xd, zbuf, ybuf, x
         torch.cuda.empty_cache()
         log("front field 100x500x500")

@@ -35,6 +35,8 @@ constexpr uint8_t kFlagConst = 1, kFlagIdx64 = 2, kFlagReorder = 4;
 // (ratio mode). The bitwise-redundancy stages run on chunks of kLcChunk bytes.
 enum : uint8_t { PIPE_HF = 0, PIPE_TP = 1, PIPE_CR = 2 };
 constexpr int kLcChunk = 16384;
+// Exact min/max (REL mode): points per work unit.
+constexpr uint64_t kMmUnit = 16384;
 
 __host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15u) & ~uint64_t(15); }
 __host__ __device__ inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }

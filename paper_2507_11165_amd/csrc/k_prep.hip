@@ -57,7 +57,6 @@ void launch_init_compress(const Job *d_jobs, int njobs, uint64_t max_chunks, Cou
 // Exact min/max (REL mode): ordered 32-bit keys reduced with atomics, so the
 // result does not depend on the order of reduction; NaN/Inf raise a flag.
 // ---------------------------------------------------------------------------
-constexpr uint64_t kMmUnit = 16384; // elements per work unit
 
 __device__ inline uint32_t wave_min_u32(uint32_t v)
 {

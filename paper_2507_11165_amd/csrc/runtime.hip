@@ -97,6 +97,7 @@ struct hiz_ctx {
     uint64_t gclock = 0;
     uint64_t graph_builds = 0, graph_replays = 0;
     hipEvent_t done = nullptr;
+    hipEvent_t chain = nullptr; // end event of the previous timed launch of the current sequence
     Batch batch;
     uint8_t *scratch = nullptr; // this device's copy of the allocation-free call's scratch array
 };
@@ -220,21 +221,23 @@ int stat_index(hiz_ctx *c, const char *name)
 }
 
 // HIP events around one launch on the launch stream; off while a graph is
-// being captured (events would become graph nodes).
+// being captured (events would become graph nodes). Within a launch sequence
+// (chained scopes, back to back on one stream) a launch's start event is the
+// previous launch's end event, so each launch records one event.
 struct Scope {
     hiz_ctx *c;
     hipStream_t s;
     Pending p;
-    bool on;
-    Scope(hiz_ctx *c_, hipStream_t s_, const char *name, bool allow = true)
-        : c(c_), s(s_), on(c_->profiling && allow)
+    bool on, chained;
+    Scope(hiz_ctx *c_, hipStream_t s_, const char *name, bool allow = true, bool chained_ = false)
+        : c(c_), s(s_), on(c_->profiling && allow), chained(chained_)
     {
         if (on) {
             p.stat = stat_index(c, name);
-            p.a = take_event(c);
+            p.a = chained && c->chain ? c->chain : take_event(c);
             p.b = take_event(c);
             on = p.a && p.b;
-            if (on)
+            if (on && p.a != c->chain)
                 hipEventRecord(p.a, s);
         }
     }
@@ -243,6 +246,8 @@ struct Scope {
         if (on) {
             hipEventRecord(p.b, s);
             c->pending.push_back(p);
+            if (chained)
+                c->chain = p.b;
         }
     }
 };
@@ -635,7 +640,7 @@ hiz_status plan_compress(const float *d_field, const uint64_t dims[3], int mode,
     J.eb = eb;
     memcpy(J.cfg_forced, p.level_cfg, sizeof(J.cfg_forced));
     J.idx_bytes = N < (1ull << 32) ? 4 : 8;
-    J.n_mm = mode == HIZ_REL ? cdiv(N, 16384) : 0;
+    J.n_mm = mode == HIZ_REL ? cdiv(N, kMmUnit) : 0;
     const uint64_t n_full = (uint64_t)J.n_full[0] * J.n_full[1] * J.n_full[2];
     if (J.tune && n_full > 0) {
         // Sec. 5.1.3: about 0.2 % of the points, in whole full blocks
@@ -915,24 +920,25 @@ void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, hipS
                       bool prof)
 {
     hipMemcpyAsync(L.d_jobs, L.h_jobs, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
+    c->chain = nullptr;
     {
-        Scope sc(c, s, "init", prof);
+        Scope sc(c, s, "init", prof, true);
         launch_init_compress(L.d_jobs, nj, std::max(T.max_groups, T.max_clear), L.d_cnt, s);
     }
     if (T.mm) {
-        Scope sc(c, s, "minmax", prof);
+        Scope sc(c, s, "minmax", prof, true);
         launch_minmax(L.d_jobs, nj, T.mm, c->cus * 8, s);
     }
     {
-        Scope sc(c, s, "eps", prof);
+        Scope sc(c, s, "eps", prof, true);
         launch_eps(L.d_jobs, nj, s);
     }
     if (T.tune) {
-        Scope sc(c, s, "tune", prof);
+        Scope sc(c, s, "tune", prof, true);
         launch_tune(L.d_jobs, nj, T.tune, s);
     }
     {
-        Scope sc(c, s, "tune_pick", prof);
+        Scope sc(c, s, "tune_pick", prof, true);
         launch_tune_pick(L.d_jobs, nj, s);
     }
     // the tile kernels: one launch per tile depth present
@@ -943,36 +949,37 @@ void enqueue_compress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, hipS
         const Job *dj = L.d_jobs + T.jlo[d];
         const int nd = T.jhi[d] - T.jlo[d];
         {
-            Scope sc(c, s, "coarse", prof);
+            Scope sc(c, s, "coarse", prof, true);
             launch_coarse(dj, nd, T.tlo[d], T.thi[d], tz, true, s);
         }
         {
-            Scope sc(c, s, "predict_quant", prof);
+            Scope sc(c, s, "predict_quant", prof, true);
             launch_predict(dj, nd, T.tlo[d], T.thi[d], tz,
                            predict_grid(c, tz, T.thi[d] - T.tlo[d], false), depth_counters(L, d),
                            s);
         }
     }
     if (T.reorder) {
-        Scope sc(c, s, "reorder", prof);
+        Scope sc(c, s, "reorder", prof, true);
         launch_reorder(L.d_jobs, nj, T.max_n, false, s);
     }
     {
-        Scope sc(c, s, "codebook", prof);
+        Scope sc(c, s, "codebook", prof, true);
         launch_codebook(L.d_jobs, nj, s);
     }
     if (T.chunks) {
-        Scope sc(c, s, "encode", prof);
+        Scope sc(c, s, "encode", prof, true);
         launch_encode(L.d_jobs, nj, T.chunks, T.groups, L.d_cnt, encode_grid(c), s);
     }
     if (T.ou) {
-        Scope sc(c, s, "outliers", prof);
+        Scope sc(c, s, "outliers", prof, true);
         launch_outliers(L.d_jobs, nj, T.ou, L.d_cnt, s);
     }
     if (T.lc) {
-        Scope sc(c, s, "lc_encode", prof);
+        Scope sc(c, s, "lc_encode", prof, true);
         launch_lc_encode(L.d_jobs, nj, T.lc, L.d_cnt, s);
     }
+    c->chain = nullptr;
     launch_gather_results(L.d_jobs, nj, L.d_res, s);
     hipMemcpyAsync(L.h_res, L.d_res, (size_t)kResultBytes * nj, hipMemcpyDeviceToHost, s);
 }
@@ -982,28 +989,29 @@ void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, hi
                         bool prof)
 {
     hipMemcpyAsync(L.d_jobs, L.h_jobs, sizeof(Job) * nj, hipMemcpyHostToDevice, s);
+    c->chain = nullptr;
     {
-        Scope sc(c, s, "init_dec", prof);
+        Scope sc(c, s, "init_dec", prof, true);
         launch_init_decompress(L.d_jobs, nj, std::max(T.max_dblk, T.max_clear), L.d_cnt, s);
     }
     if (T.dblk) {
-        Scope sc(c, s, "dec_tables", prof);
+        Scope sc(c, s, "dec_tables", prof, true);
         launch_dec_tables(L.d_jobs, nj, s);
     }
     if (T.lc) {
-        Scope sc(c, s, "lc_decode", prof);
+        Scope sc(c, s, "lc_decode", prof, true);
         launch_lc_decode(L.d_jobs, nj, T.lc, L.d_cnt, s);
     }
     if (T.dblk) {
-        Scope sc(c, s, "decode", prof);
+        Scope sc(c, s, "decode", prof, true);
         launch_decode(L.d_jobs, nj, T.dblk, L.d_cnt, s);
     }
     if (T.reorder) {
-        Scope sc(c, s, "unreorder", prof);
+        Scope sc(c, s, "unreorder", prof, true);
         launch_reorder(L.d_jobs, nj, T.max_n, true, s);
     }
     if (T.out) {
-        Scope sc(c, s, "scatter", prof);
+        Scope sc(c, s, "scatter", prof, true);
         launch_scatter(L.d_jobs, nj, T.out, s);
     }
     for (int d = 0; d < kTileDepths; d++) {
@@ -1013,16 +1021,17 @@ void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, hi
         const Job *dj = L.d_jobs + T.jlo[d];
         const int nd = T.jhi[d] - T.jlo[d];
         {
-            Scope sc(c, s, "coarse_rec", prof);
+            Scope sc(c, s, "coarse_rec", prof, true);
             launch_coarse(dj, nd, T.tlo[d], T.thi[d], tz, false, s);
         }
         {
-            Scope sc(c, s, "reconstruct", prof);
+            Scope sc(c, s, "reconstruct", prof, true);
             launch_reconstruct(dj, nd, T.tlo[d], T.thi[d], tz,
                                predict_grid(c, tz, T.thi[d] - T.tlo[d], true),
                                depth_counters(L, d), s);
         }
     }
+    c->chain = nullptr;
     launch_gather_results(L.d_jobs, nj, L.d_res, s);
     hipMemcpyAsync(L.h_res, L.d_res, (size_t)kResultBytes * nj, hipMemcpyDeviceToHost, s);
 }
@@ -1567,7 +1576,7 @@ uint64_t hiz_workspace_bound(const uint64_t dims[3])
     const uint64_t chunks = cdiv(N, 256);
     const uint64_t groups = cdiv(chunks, kEncGroupChunks);
     const uint64_t tiles = cdiv(dims[0], kAnchor) * cdiv(dims[1], kAnchor) * cdiv(dims[2], kAnchor);
-    const uint64_t mm = std::max<uint64_t>(cdiv(N, 16384), tiles);
+    const uint64_t mm = std::max<uint64_t>(cdiv(N, kMmUnit), tiles);
     const uint64_t per_job = sizeof(Job) + kResultBytes + sizeof(FieldState) + 12 * 256;
     // per-tile coarse-level slots (values and codes of the even-point grid)
     uint64_t coarse = 0;
