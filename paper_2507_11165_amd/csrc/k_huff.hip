@@ -808,42 +808,82 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     const uint32_t nsym = (uint32_t)(i1 - i0);
     const uint32_t maxlen = s_maxlen;
     const uint64_t wend = start + wc;
-    // Payload words reach the decoder through a per-lane ring of kRing words in
-    // LDS. Symbols are decoded in rounds of 16, the same for every lane of the
-    // wave; at each round boundary the words prefetched during the previous
-    // round are committed to the ring and, if the ring has room, the next 16
-    // are requested. A round consumes at most 16 words (codewords are at most
-    // 32 bits), so the ring holding 16 words at a round's start is enough; a
-    // lane below that (codes far longer than usual) refills synchronously.
-    // Words past the chunk's end read as zero. Slot i of this lane's ring is
-    // s_win[i * kDecChunks + t]: the lanes of a wave touch consecutive words
-    // whatever slots they are at (no bank conflicts).
+    // Payload words reach the decoder through a per-lane ring of kRing words
+    // in LDS, filled from 16-byte aligned groups of four words. The payload
+    // starts 16-byte aligned, so a group whose first word lies in the payload
+    // stays inside that word's page. Relative index q counts words from
+    // base0, the chunk's first word rounded down to a group; word q sits in
+    // slot q % kRing of this lane's ring, at s_win[(q % kRing) * kDecChunks +
+    // t], so the lanes of a wave touch consecutive words whatever slots they
+    // are at. Words before the chunk's start are never taken; words past its
+    // end (the next chunk's, or those of a shared line) are decoded as
+    // padding, which only the tail rounds see and none of whose codes count.
+    //
+    // Symbols are decoded in rounds of 8 steps, the same for every lane of
+    // the wave. At a round's end a lane with room for 16 more words in its
+    // ring requests them into register set r % kSets (r the round), and they
+    // enter the ring at the start of round r + kSets, when that set comes
+    // round again: the loads have kSets - 1 rounds to arrive. Every round issues the same four
+    // 16-byte loads whether or not a lane requests (a lane that does not
+    // points them at one line that all such lanes share), so the wait for a
+    // set covers its own loads, not the later sets'. A round takes at most 8
+    // words (one per step) and reads one more ahead; a lane with fewer than
+    // kLow committed words at a round's start takes its pending sets in at
+    // once, then loads synchronously if it must (codes far longer than
+    // usual).
+    constexpr int kSets = 3;
+    // committed words a lane holds at a round's start: one per step, plus
+    // the word read ahead after the round's last step
+    constexpr uint32_t kLow = 9;
     uint32_t *ring = s_win + t;
     // this lane's 32-byte output ring; the stride is odd in words, so lanes
     // at the same position write different banks
     uint8_t *row = s_rows + t * kRowBytes;
-    // payload word idx of this chunk, 0 past its end; the load itself is never
-    // skipped (its index is clamped inside the payload), so a run of them is
-    // issued back to back without a branch or a wait between them
-    const uint64_t wlast = wend > start ? wend - 1 : min(start, pw - 1);
-    auto raw = [&](uint64_t idx) -> uint32_t { return words[idx < wend ? idx : wlast]; };
-    auto word = [&](uint64_t idx) -> uint32_t { return idx < wend ? raw(idx) : 0u; };
-    uint64_t wfetch = start;
-    uint32_t rp = 0, wp = 0; // words read from / written to the ring so far
-    uint32_t pre[16];
-    uint64_t pre_base = 0; // payload index of pre[0]
-    bool pending = false;
+    const uint64_t base0 = start & ~3ull;
+    const uint32_t r0 = (uint32_t)(start - base0);
+    // payload words from base0 on (at least 1: start < pw), capped
+    const uint32_t pwr = (uint32_t)min(pw - base0, (uint64_t)0x7FFFFFF0u);
+    const uint32_t pwr4 = (pwr + 3u) & ~3u;
+    HIZ_GLOBAL const uint32_t *wb = words + base0;
+    HIZ_GLOBAL const uint8_t *shared_line = reinterpret_cast<HIZ_GLOBAL const uint8_t *>(gmem(dt->lut));
+    // the group of words q..q+3, or the shared line when not wanted or past the payload
+    auto group = [&](uint32_t q, bool live) __attribute__((always_inline)) -> uint4 {
+        return gload_u4(live && q < pwr ? reinterpret_cast<HIZ_GLOBAL const uint8_t *>(wb + q) : shared_line);
+    };
+    // words q..q+15 (q a multiple of 16) into their slots
+    auto put16 = [&](uint32_t q, const uint4 (&g)[4]) __attribute__((always_inline)) {
+        uint32_t *r = ring + (q & 16u) * kDecChunks;
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
+        for (int k = 0; k < 4; k++) {
+            r[(4 * k + 0) * kDecChunks] = g[k].x;
+            r[(4 * k + 1) * kDecChunks] = g[k].y;
+            r[(4 * k + 2) * kDecChunks] = g[k].z;
+            r[(4 * k + 3) * kDecChunks] = g[k].w;
+        }
+    };
+    static_assert(kRing == 32, "the ring holds two sets of 16 words");
+    {
+        uint4 g0[4], g1[4];
 #pragma unroll
-        for (int j = 0; j < 16; j++)
-            pre[j] = word(wfetch + j);
-#pragma unroll
-        for (int j = 0; j < 16; j++)
-            ring[(16 * h + j) * kDecChunks] = pre[j];
-        wfetch += 16;
+        for (int k = 0; k < 4; k++) {
+            g0[k] = group(4 * k, true);
+            g1[k] = group(16 + 4 * k, true);
+        }
+        put16(0, g0);
+        put16(16, g1);
     }
-    wp = 32;
+    // words up to wp are in the ring, up to wq in the ring or requested; rp
+    // is the next word the bit buffer takes; wp, wq and the sets' first
+    // words stay multiples of 16
+    uint32_t wp = kRing, wq = kRing, rp;
+    uint4 pre[kSets][4];
+    uint32_t pq[kSets];
+    bool pend[kSets];
+#pragma unroll
+    for (int s = 0; s < kSets; s++) {
+        pq[s] = 0;
+        pend[s] = false;
+    }
     uint32_t zeros = 0;
     bool bad = false;
     // Ends of the code ranges of the lengths past the table (kLutBits + 1 ..
@@ -851,19 +891,27 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     // used): the same for every lane, kept in scalar registers. A code
     // longer than the table has length kLutBits + 1 plus the number of these
     // its window is above.
-    uint32_t lim[kMaxCodeLen - kLutBits - 1];
+    uint32_t lim[kMaxCodeLen - kLutBits - 1], base3[3];
 #pragma unroll
     for (int k = 0; k < kMaxCodeLen - kLutBits - 1; k++) {
         const int Lk = kLutBits + 1 + k;
         lim[k] = __builtin_amdgcn_readfirstlane((uint32_t)Lk < maxlen ? limit[Lk] - 1u : 0xFFFFFFFFu);
     }
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        base3[k] = __builtin_amdgcn_readfirstlane(base[kLutBits + 1 + k]);
     // Bit buffer: the next nb (32..63 before a step) payload bits, first bit
     // at the top of hi, then lo; zeros below them. The word after the buffer
     // waits in nextw, so a refill never waits for LDS; rp counts words taken
     // out of the ring. e is the table entry of the buffer's first kLutBits
     // bits, read a step ahead.
-    uint32_t hi = ring[0], lo = ring[kDecChunks], nextw = ring[2 * kDecChunks];
-    rp = 3;
+    uint32_t hi = ring[(r0 & (kRing - 1)) * kDecChunks], lo = ring[((r0 + 1) & (kRing - 1)) * kDecChunks],
+             nextw = ring[((r0 + 2) & (kRing - 1)) * kDecChunks];
+    rp = r0 + 3;
+    // the ring word at rp, read a step ahead: a refill takes it as the new
+    // nextw. It is read right after the step's table read, so the wait for
+    // the entry at the next step's start leaves it in flight
+    uint32_t nw = ring[(rp & (kRing - 1)) * kDecChunks];
     int nb = 64;
     uint32_t e = lut[hi >> (32 - kLutBits)];
     uint32_t pos = 0, flushed = 0; // codes decoded (padding past the end included) / stored
@@ -874,26 +922,37 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     // entry takes at most kLutBits of the 32 or more valid bits), writes the
     // two symbol bytes at the lane's output position (a second byte past the
     // entry's count is overwritten later) and advances by the count, then
-    // refills by masks when fewer than 32 bits remain. A code longer than the
-    // table takes its length from the range ends and its symbol from the
-    // sorted table, and the next entry is read again once the buffer is
-    // refilled. Past the chunk's last code the steps decode padding; in the
-    // tail rounds ub keeps the bits the chunk's own codes took.
-    auto step = [&](auto tail_tag) {
+    // refills by masks when fewer than 32 bits remain. When some lane of the
+    // wave holds a code longer than the table (SLOW, decided for the wave),
+    // that lane takes the code's length from the range ends and its symbol
+    // from the sorted table first, and every lane reads its next entry after
+    // the refill. Past the chunk's last code the steps decode
+    // padding; in the tail rounds ub keeps the bits the chunk's own codes
+    // took, and only the chunk's own codes can be invalid.
+    auto step_as = [&](auto tail_tag, auto slow_tag) __attribute__((always_inline)) {
         constexpr bool TAIL = decltype(tail_tag)::value;
-        const uint32_t nw = ring[(rp & (kRing - 1)) * kDecChunks];
-        const bool slow = e == 0u;
-        if (__builtin_expect(__any(slow), 0) && slow) {
-            uint32_t L = kLutBits + 1;
+        constexpr bool SLOW = decltype(slow_tag)::value;
+        const bool slow = SLOW && e == 0u;
+        if (SLOW && slow) {
+            // the three lengths past the table first (their sorted-table
+            // bases are in scalar registers); longer codes only when some
+            // lane of the wave holds one
+            uint32_t L = kLutBits + 1 + (hi > lim[0] ? 1u : 0u) + (hi > lim[1] ? 1u : 0u) +
+                         (hi > lim[2] ? 1u : 0u);
+            uint32_t bL = hi > lim[0] ? (hi > lim[1] ? base3[2] : base3[1]) : base3[0];
+            if (__builtin_expect(__any(hi > lim[2]), 0)) {
 #pragma unroll
-            for (int k = 0; k < kMaxCodeLen - kLutBits - 1; k++)
-                L += hi > lim[k] ? 1u : 0u;
+                for (int k = 3; k < kMaxCodeLen - kLutBits - 1; k++)
+                    L += hi > lim[k] ? 1u : 0u;
+                if (L > kLutBits + 3 && L <= kMaxCodeLen)
+                    bL = base[L];
+            }
             uint32_t sym = 0;
             if (L > maxlen) {
-                bad = true;
+                bad = bad || !TAIL || pos < nsym;
                 L = 1;
             } else {
-                sym = sorted[(base[L] + (hi >> (32 - L))) & 255u];
+                sym = sorted[(bL + (hi >> (32 - L))) & 255u];
             }
             if (L == 32) {
                 // the entry can shift by at most 31: take one bit here
@@ -910,7 +969,23 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         hi = __builtin_amdgcn_alignbit(hi, lo, e);
         lo <<= tb;
         nb -= (int)tb;
-        uint32_t en = lut[hi >> (32 - kLutBits)];
+        // refill: m is all ones when fewer than 32 bits remain
+        auto refill = [&]() __attribute__((always_inline)) {
+            const uint32_t m = (uint32_t)((nb - 32) >> 31);
+            hi |= (nextw >> nb) & m;
+            lo = (__builtin_amdgcn_alignbit(nextw, 0u, (uint32_t)nb) & m) | (lo & ~m);
+            nb += (int)(m & 32u);
+            nextw = (nw & m) | (nextw & ~m);
+            rp -= m;
+        };
+        // with no long code in the wave at least 19 bits remain after the
+        // shift, so the next entry is read before the refill; otherwise
+        // after it
+        uint32_t en = 0;
+        if (!SLOW)
+            en = lut[hi >> (32 - kLutBits)];
+        else
+            refill();
         row[pos & 31] = (uint8_t)(e >> 8);
         row[(pos + 1) & 31] = (uint8_t)(e >> 16);
         const uint32_t n = (e >> 5) & 3u;
@@ -920,16 +995,18 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
             cb += tb;
         }
         pos += n;
-        // refill: m is all ones when fewer than 32 bits remain
-        const uint32_t m = (uint32_t)((nb - 32) >> 31);
-        hi |= (nextw >> nb) & m;
-        lo = (__builtin_amdgcn_alignbit(nextw, 0u, (uint32_t)nb) & m) | (lo & ~m);
-        nb += (int)(m & 32u);
-        nextw = (nw & m) | (nextw & ~m);
-        rp -= m;
-        if (__builtin_expect(__any(slow), 0) && slow)
-            en = reinterpret_cast<volatile const uint32_t *>(lut)[hi >> (32 - kLutBits)];
+        if (!SLOW)
+            refill();
+        else
+            en = lut[hi >> (32 - kLutBits)];
+        nw = ring[(rp & (kRing - 1)) * kDecChunks];
         e = en;
+    };
+    auto step = [&](auto tail_tag) __attribute__((always_inline)) {
+        if (__builtin_expect(__any(e == 0u), 0))
+            step_as(tail_tag, std::true_type{});
+        else
+            step_as(tail_tag, std::false_type{});
     };
     auto zbytes = [](uint32_t w, uint32_t valid) -> uint32_t {
         // 0x80 in each byte of w that is zero, then only the valid bytes
@@ -937,50 +1014,43 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         const uint32_t msk = valid >= 4 ? 0xFFFFFFFFu : ((1u << (8 * valid)) - 1u);
         return (uint32_t)__builtin_popcount(z & msk);
     };
-    // Rounds of 8 steps, the same for every lane of the wave, until every
-    // lane has stored its chunk. A round decodes at most 16 codes and takes
-    // at most 8 payload words.
-#pragma nounroll
-    while (__any(flushed < nsym)) {
-        // words requested a round ago enter the ring
-        if (pending) {
-#pragma unroll
-            for (int j = 0; j < 16; j++)
-                ring[((wp + j) & (kRing - 1)) * kDecChunks] = pre_base + j < wend ? pre[j] : 0u;
+    // One round: set S's words, requested at the end of the round kSets
+    // rounds back, enter the ring; the ring is topped up if it runs low; 8
+    // steps; a lane holding 16 codes, or its chunk's last ones, stores them
+    // from its 32-byte output ring, counting code-0 bytes on the way; set S
+    // is requested again.
+    auto round = [&](auto set_tag) __attribute__((always_inline)) {
+        constexpr int S = decltype(set_tag)::value;
+        if (pend[S]) {
+            put16(pq[S], pre[S]);
             wp += 16;
-            pending = false;
+            pend[S] = false;
         }
-        if (wp - rp < 16) {
-            // rare (codes far longer than usual): synchronous top-up
-            uint32_t r[16];
+        if (__builtin_expect(__any(wp - rp < kLow), 0)) {
+            // the pending sets in request order, then a synchronous load
 #pragma unroll
-            for (int j = 0; j < 16; j++)
-                r[j] = word(wfetch + j);
+            for (int i = 1; i < kSets; i++) {
+                const int S2 = (S + i) % kSets;
+                if (wp - rp < kLow && pend[S2]) {
+                    put16(pq[S2], pre[S2]);
+                    wp += 16;
+                    pend[S2] = false;
+                }
+            }
+            if (wp - rp < kLow) {
+                uint4 g[4];
 #pragma unroll
-            for (int j = 0; j < 16; j++)
-                ring[((wp + j) & (kRing - 1)) * kDecChunks] = r[j];
-            wfetch += 16;
-            wp += 16;
-        }
-        // request the next 16 words: decided per lane, but when any lane of
-        // the wave asks every lane loads (a uniform branch keeps the loads
-        // in flight until the next round commits them)
-        const bool want = wp - rp <= kRing - 16;
-        if (__any(want)) {
-            // raw words: the words past the chunk's end are zeroed when they
-            // are committed, so nothing here waits for the loads
-#pragma unroll
-            for (int j = 0; j < 16; j++)
-                pre[j] = raw(wfetch + j);
-            pre_base = wfetch;
-            if (want)
-                wfetch += 16;
-            pending = want;
+                for (int k = 0; k < 4; k++)
+                    g[k] = group(wq + 4 * k, true);
+                put16(wq, g);
+                wq += 16;
+                wp += 16;
+            }
         }
         // tail rounds from the first round in which some lane may reach its end
         if (!tail && __any(pos + 16 >= nsym)) {
             tail = true;
-            cb = 32u * (rp - 1) - (uint32_t)nb;
+            cb = 32u * (rp - r0 - 1) - (uint32_t)nb;
         }
         if (tail) {
 #pragma unroll
@@ -991,8 +1061,6 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
             for (int k = 0; k < 8; k++)
                 step(std::false_type{});
         }
-        // a lane holding 16 codes, or its chunk's last ones, stores them from
-        // its 32-byte output ring; code-0 bytes are counted on the way
         if (flushed < nsym && (pos >= flushed + 16 || pos >= nsym)) {
             const uint32_t *rw = reinterpret_cast<const uint32_t *>(row + (flushed & 16));
             const uint32_t w0 = rw[0], w1 = rw[1], w2 = rw[2], w3 = rw[3];
@@ -1010,9 +1078,43 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
             }
             flushed += 16;
         }
+        // request, at the round's end, where any wait it needs is for LDS
+        // work that the next step waits for anyway: words up to wq - rp + 16
+        // fit the ring. The four groups are loaded from one base address at
+        // offsets 0, 16, 32 and 48 bytes, each offset capped so that the
+        // group starts inside the payload (a capped group repeats an earlier
+        // one: its words are past the payload's end and only decoded as
+        // padding); a lane that does not request, or whose words are all
+        // past the payload, reads the shared line
+        const bool want = wq - rp <= kRing - 16;
+        {
+            const bool live = want && wq < pwr;
+            HIZ_GLOBAL const uint8_t *src =
+                live ? reinterpret_cast<HIZ_GLOBAL const uint8_t *>(wb + wq) : shared_line;
+            const uint32_t cap = live ? 4u * min(12u, pwr4 - 4u - wq) : 48u;
+            pre[S][0] = gload_u4(src);
+#pragma unroll
+            for (int k = 1; k < 4; k++)
+                pre[S][k] = gload_u4(src + min(16u * k, cap));
+        }
+        pq[S] = wq;
+        pend[S] = want;
+        wq += want ? 16u : 0u;
+    };
+    // rounds, the same for every lane of the wave, until every lane has
+    // stored its chunk; unrolled by kSets so that each set is a fixed group
+    // of registers, with no exit between them (a lane past its chunk's end
+    // decodes padding and stores nothing), so that the loop is entered from
+    // one place only and each set's wait counts the later sets' loads
+    static_assert(kSets == 3, "the loop below runs three sets");
+#pragma nounroll
+    while (__any(flushed < nsym)) {
+        round(std::integral_constant<int, 0>{});
+        round(std::integral_constant<int, 1>{});
+        round(std::integral_constant<int, 2>{});
     }
     // bits taken by the chunk's codes
-    const uint64_t used = tail ? (uint64_t)ub : 32ull * (rp - 1) - (uint64_t)nb;
+    const uint64_t used = tail ? (uint64_t)ub : 32ull * (rp - r0 - 1) - (uint64_t)nb;
     if (bad || (used + 31) / 32 != wc)
         atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
     if (zeros)
