@@ -202,7 +202,13 @@ void launch_gather_results(const Job *d_jobs, int njobs, void *d_dst, hipStream_
 void launch_init_decompress(const Job *d_jobs, int njobs, uint64_t max_blocks, Counters *cnt,
                             hipStream_t s);
 void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s);
-void launch_decode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, hipStream_t s);
+// The decoder's work units are sub-blocks of kDecSub chunks, an even number
+// per field, so that a workgroup of 2 * kDecSub lanes can take a pair of one
+// field. `cus` picks the workgroup size: kDecSub lanes (one workgroup per
+// unit) while the units fit the compute units, else 2 * kDecSub.
+constexpr int kDecSub = 256;
+__host__ __device__ inline uint64_t dec_subblocks(uint64_t chunks) { return 2 * cdiv(chunks, 2 * kDecSub); }
+void launch_decode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, int cus, hipStream_t s);
 void launch_scatter(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s);
 void launch_reconstruct(const Job *d_jobs, int njobs, uint64_t lo, uint64_t hi, int tile_z,
                         int grid, uint32_t *ctr, hipStream_t s);

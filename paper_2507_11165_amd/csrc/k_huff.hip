@@ -722,22 +722,27 @@ void launch_dec_tables(const Job *d_jobs, int njobs, hipStream_t s)
     hipLaunchKernelGGL(k_dec_tables, dim3(kDecTableParts, njobs), dim3(256), 0, s, d_jobs, njobs);
 }
 
-// One thread per chunk; a workgroup takes 256 consecutive chunks, finds its
-// payload offset by look-back over the stored word counts, and each thread
-// decodes its chunk sequentially with the LDS lookup table, up to three
-// codes per table read.
-constexpr int kDecChunks = 256;
+// One thread per chunk; a workgroup takes kDecChunks consecutive chunks
+// (one or two sub-blocks of one field), finds its payload offset by
+// look-back over the stored word counts, and each thread decodes its chunk
+// sequentially with the LDS lookup table, up to two codes per table read.
 constexpr int kRing = 32;      // payload words of a decoder lane's LDS ring (a power of two)
-constexpr int kRowBytes = 36;  // a lane's LDS output ring: 32 codes, padding (odd in words)
+constexpr int kRowRing = 64;   // a lane's LDS output ring of codes (a power of two)
+constexpr int kRowBytes = 68;  // its stride: the ring and padding (odd in words)
+constexpr int kFlush = 32;     // codes a lane stores at once: one 32-byte aligned piece
 
-__global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, int njobs,
-                                                uint64_t total, Counters *cnt)
+template <int kDecChunks>
+__global__ __launch_bounds__(kDecChunks) void k_decode(const Job *__restrict__ jobs, int njobs,
+                                                       uint64_t total, Counters *cnt)
 {
+    static_assert(kDecChunks % kDecSub == 0 && kDecChunks >= 256, "whole sub-blocks");
+    constexpr int kWaves = kDecChunks / 64;
+    constexpr int kSubs = kDecChunks / kDecSub;
     __shared__ __align__(16) uint32_t lut[1 << kLutBits];
     __shared__ uint32_t limit[kMaxCodeLen + 2], base[kMaxCodeLen + 2];
     __shared__ uint8_t sorted[256];
     __shared__ uint32_t s_id, s_maxlen;
-    __shared__ uint64_t s_wsum[4];
+    __shared__ uint64_t s_wsum[kWaves];
     __shared__ uint64_t s_base;
     __shared__ uint32_t s_win[kDecChunks * kRing];
     __shared__ __align__(16) uint8_t s_rows[kDecChunks * kRowBytes];
@@ -745,25 +750,28 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     if (t == 0)
         s_id = atomicAdd(&cnt->dec_next, 1u);
     __syncthreads();
+    // total counts sub-blocks; each field has an even number of them
     const uint64_t id = s_id;
-    if (id >= total)
+    if (id * kSubs >= total)
         return;
-    const Job &J = jobs[find_job<WK_DBLK>(jobs, njobs, id)];
+    const Job &J = jobs[find_job<WK_DBLK>(jobs, njobs, id * kSubs)];
     const DecTables *dt = J.dt;
     {
         HIZ_GLOBAL const uint8_t *src = reinterpret_cast<HIZ_GLOBAL const uint8_t *>(gmem(dt->lut));
         uint4 *dst = reinterpret_cast<uint4 *>(lut);
-        for (int i = t; i < (1 << kLutBits) / 4; i += 256)
+        for (int i = t; i < (1 << kLutBits) / 4; i += kDecChunks)
             dst[i] = gload_u4(src + 16 * i);
     }
     if (t <= kMaxCodeLen) {
         limit[t] = dt->limit[t];
         base[t] = dt->base[t];
     }
-    sorted[t] = dt->sorted[t];
+    if (t < 256)
+        sorted[t] = dt->sorted[t];
     if (t == 0)
         s_maxlen = dt->maxlen;
-    const uint64_t lb = id - J.dblk_begin;
+    // this workgroup's place among the field's workgroups (the look-back index)
+    const uint64_t lb = (id * kSubs - J.dblk_begin) / kSubs;
     const uint64_t chunk = lb * kDecChunks + t;
     HIZ_GLOBAL const uint32_t *counts =
         reinterpret_cast<HIZ_GLOBAL const uint32_t *>(gmem(J.stream) + kOffChunks);
@@ -778,7 +786,7 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         s_wsum[wv] = incl;
     __syncthreads();
     uint64_t before = 0, blk_total = 0;
-    for (int k = 0; k < 4; k++) {
+    for (int k = 0; k < kWaves; k++) {
         before += (k < wv) ? s_wsum[k] : 0;
         blk_total += s_wsum[k];
     }
@@ -836,8 +844,8 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     // the word read ahead after the round's last step
     constexpr uint32_t kLow = 9;
     uint32_t *ring = s_win + t;
-    // this lane's 32-byte output ring; the stride is odd in words, so lanes
-    // at the same position write different banks
+    // this lane's output ring of kRowRing codes; the stride is odd in
+    // words, so lanes at the same position write different banks
     uint8_t *row = s_rows + t * kRowBytes;
     const uint64_t base0 = start & ~3ull;
     const uint32_t r0 = (uint32_t)(start - base0);
@@ -986,8 +994,8 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
             en = lut[hi >> (32 - kLutBits)];
         else
             refill();
-        row[pos & 31] = (uint8_t)(e >> 8);
-        row[(pos + 1) & 31] = (uint8_t)(e >> 16);
+        row[pos & (kRowRing - 1)] = (uint8_t)(e >> 8);
+        row[(pos + 1) & (kRowRing - 1)] = (uint8_t)(e >> 16);
         const uint32_t n = (e >> 5) & 3u;
         if (TAIL) {
             // a second code past the chunk's end is padding: only the first counts
@@ -1016,9 +1024,9 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
     };
     // One round: set S's words, requested at the end of the round kSets
     // rounds back, enter the ring; the ring is topped up if it runs low; 8
-    // steps; a lane holding 16 codes, or its chunk's last ones, stores them
-    // from its 32-byte output ring, counting code-0 bytes on the way; set S
-    // is requested again.
+    // steps; a lane holding kFlush codes, or its chunk's last ones, stores
+    // them from its output ring, counting code-0 bytes on the way; set S is
+    // requested again.
     auto round = [&](auto set_tag) __attribute__((always_inline)) {
         constexpr int S = decltype(set_tag)::value;
         if (pend[S]) {
@@ -1061,22 +1069,35 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
             for (int k = 0; k < 8; k++)
                 step(std::false_type{});
         }
-        if (flushed < nsym && (pos >= flushed + 16 || pos >= nsym)) {
-            const uint32_t *rw = reinterpret_cast<const uint32_t *>(row + (flushed & 16));
-            const uint32_t w0 = rw[0], w1 = rw[1], w2 = rw[2], w3 = rw[3];
-            const uint32_t cnt = min(16u, nsym - flushed);
+        // a round decodes at most 16 codes, so a lane holds fewer than
+        // kFlush + 16 unstored codes at a round's end and one store per
+        // round keeps up; each store is one whole 32-byte aligned piece of
+        // the chunk's codes (the chunk's last piece may be shorter)
+        static_assert(kFlush + 16 + 1 <= kRowRing, "the output ring holds a round's codes");
+        if (flushed < nsym && (pos >= flushed + kFlush || pos >= nsym)) {
+            const uint8_t *rb = row + (flushed & (kRowRing - 1));
+            const uint32_t *rw = reinterpret_cast<const uint32_t *>(rb);
+            uint32_t w[kFlush / 4];
+#pragma unroll
+            for (int k = 0; k < kFlush / 4; k++)
+                w[k] = rw[k];
+            const uint32_t cnt = min((uint32_t)kFlush, nsym - flushed);
             const uint64_t o = i0 + flushed;
-            if (cnt == 16) {
-                gstore_u4(codes + o, make_uint4(w0, w1, w2, w3));
-                zeros += zbytes(w0, 4) + zbytes(w1, 4) + zbytes(w2, 4) + zbytes(w3, 4);
+            if (cnt == kFlush) {
+#pragma unroll
+                for (int k = 0; k < kFlush / 16; k++)
+                    gstore_u4(codes + o + 16 * k, make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]));
+#pragma unroll
+                for (int k = 0; k < kFlush / 4; k++)
+                    zeros += zbytes(w[k], 4);
             } else {
-                const uint8_t *rb = row + (flushed & 16);
                 for (uint32_t k = 0; k < cnt; k++)
                     codes[o + k] = rb[k];
-                zeros += zbytes(w0, cnt) + zbytes(w1, cnt > 4 ? cnt - 4 : 0) +
-                         zbytes(w2, cnt > 8 ? cnt - 8 : 0) + zbytes(w3, cnt > 12 ? cnt - 12 : 0);
+#pragma unroll
+                for (int k = 0; k < kFlush / 4; k++)
+                    zeros += zbytes(w[k], cnt > 4u * k ? cnt - 4u * k : 0u);
             }
-            flushed += 16;
+            flushed += kFlush;
         }
         // request, at the round's end, where any wait it needs is for LDS
         // work that the next step waits for anyway: words up to wq - rp + 16
@@ -1121,12 +1142,20 @@ __global__ __launch_bounds__(256) void k_decode(const Job *__restrict__ jobs, in
         atomicAdd((unsigned long long *)&st->zeros_seen, (unsigned long long)zeros);
 }
 
-void launch_decode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, hipStream_t s)
+void launch_decode(const Job *d_jobs, int njobs, uint64_t total, Counters *cnt, int cus, hipStream_t s)
 {
     if (total == 0)
         return;
-    hipLaunchKernelGGL(k_decode, dim3((uint32_t)total), dim3(kDecChunks), 0, s, d_jobs, njobs,
-                       total, cnt);
+    // one workgroup of kDecSub lanes per compute unit while the sub-blocks
+    // fit the device; past that, workgroups of two sub-blocks share one
+    // table among twice the lanes (one workgroup per compute unit either
+    // way, by their LDS)
+    if (total <= (uint64_t)cus)
+        hipLaunchKernelGGL(k_decode<kDecSub>, dim3((uint32_t)total), dim3(kDecSub), 0, s, d_jobs,
+                           njobs, total, cnt);
+    else
+        hipLaunchKernelGGL(k_decode<2 * kDecSub>, dim3((uint32_t)(total / 2)), dim3(2 * kDecSub), 0,
+                           s, d_jobs, njobs, total, cnt);
 }
 
 // Outliers go to their positions in the output before reconstruction reads

@@ -701,7 +701,7 @@ void plan_decompress(const Parsed &P, const void *d_in, uint64_t in_size, float 
     memcpy(J.cfg_forced, P.info.level_cfg, sizeof(J.cfg_forced));
     J.idx_bytes = (uint8_t)P.idx_bytes;
     J.n_tiles = (uint64_t)J.nb[0] * J.nb[1] * J.ntz;
-    J.n_dblk = cdiv(J.n_chunks, 256);
+    J.n_dblk = dec_subblocks(J.n_chunks);
     set_full_tiles(J, tz);
     J.off_oidx = P.off_oidx;
     J.off_oval = P.off_oval;
@@ -1004,7 +1004,7 @@ void enqueue_decompress(hiz_ctx *c, const Layout &L, int nj, const Totals &T, hi
     }
     if (T.dblk) {
         Scope sc(c, s, "decode", prof, true);
-        launch_decode(L.d_jobs, nj, T.dblk, L.d_cnt, s);
+        launch_decode(L.d_jobs, nj, T.dblk, L.d_cnt, c->cus, s);
     }
     if (T.reorder) {
         Scope sc(c, s, "unreorder", prof, true);
@@ -1589,7 +1589,7 @@ uint64_t hiz_workspace_bound(const uint64_t dims[3])
     const uint64_t lc = cdiv(4 * (N + chunks), kLcChunk);
     const uint64_t pipes = N + 4 * (N + chunks) + 16 * lc + 4 * 256;
     const uint64_t comp = per_job + N + 16 * groups + 16 * chunks + 8 * mm + coarse + pipes;
-    const uint64_t dec = per_job + sizeof(DecTables) + N + 8 * cdiv(chunks, 256) + coarse + pipes;
+    const uint64_t dec = per_job + sizeof(DecTables) + N + 8 * dec_subblocks(chunks) + coarse + pipes;
     return std::max(comp, dec);
 }
 
