@@ -948,6 +948,8 @@ __device__ __forceinline__ void coarse_place(const CoarseRegs<TZ, NT> &r, int ti
 {
     using TF = TileShape<TZ>;
     using TC = TileShape<TZ, 8>;
+    // LDS addresses are recomputed per tile, not kept (or spilled) across the tile loop
+    asm volatile("" : "+v"(tid));
 #pragma unroll
     for (int k = 0; k < r.IV; k++) {
         const int i = tid + NT * k;
@@ -1057,6 +1059,8 @@ __device__ __forceinline__ void tile_place(const TileRegs<TZ> &f, float *__restr
 {
     using TS = TileShape<TZ>;
     using TR = TileRegs<TZ>;
+    // LDS addresses are recomputed per tile, not kept (or spilled) across the tile loop
+    asm volatile("" : "+v"(tid));
     if (f.vec) {
 #pragma unroll
         for (int k = 0; k < TR::IP; k++) {
