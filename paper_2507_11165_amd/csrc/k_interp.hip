@@ -461,11 +461,15 @@ __device__ __forceinline__ void run_line(const LineGroup &G, int l, int S, float
 // start and the eight targets run unrolled; only the cross-axis sample
 // presence (fixed per line) is a run-time choice. Arithmetic is the same as
 // in do_line, operation for operation.
-template <int TZ, int A, int MB, int MC, int CUB, bool COMP>
+// KB, KE: the line's targets KB..KE-1 (a half line when a sub-step has too
+// few lines to fill the workgroup), with the knowns their stencils read.
+template <int TZ, int A, int MB, int MC, int CUB, bool COMP, int KB = 0, int KE = 8>
 __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__restrict__ cb,
                                            const uint8_t *__restrict__ cl, const Geo &g, int x0,
                                            int y0, int z0, const QParams &q)
 {
+    static_assert(0 <= KB && KB < KE && KE <= 8, "targets of one line");
+    constexpr int JB = KB > 0 ? KB - 1 : 0, JE = KE < 8 ? KE + 1 : 8; // knowns JB..JE
     using TS = TileShape<TZ>;
     constexpr int B = (A == 0) ? 1 : 0;
     constexpr int C = (A == 2) ? 1 : 2;
@@ -501,20 +505,50 @@ __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__res
     const int cst = own ? cstep : 0;
     float w[9];
 #pragma unroll
-    for (int j = 0; j < 9; j++)
+    for (int j = JB; j <= JE; j++)
         w[j] = vl[2 * j * stA];
     float xv[8];
     uint8_t cc[8];
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
+    for (int k = KB; k < KE; k++) {
         xv[k] = vl[(2 * k + 1) * stA];
         if constexpr (!COMP)
             cc[k] = cl[li0 + (2 * k + 1) * stA];
     }
-    static_for<0, 8>([&](auto kc) {
+    // Cross-axis samples of target k, read one target ahead: the next
+    // target's reads are issued before this target's value is written back,
+    // so that their latency overlaps this target's arithmetic (no target of a
+    // sub-step reads another's result, so the order is free).
+    struct XS {
+        CrossSamples b, c;
+    };
+    auto load_cross = [&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        const int li = li0 + (2 * k + 1) * stA;
+        XS r{};
+        if constexpr (MB) {
+            r.b.b = v[li - stB];
+            r.b.a = v[li + oBa];
+            r.b.c = v[li + stB];
+            r.b.d = v[li + oBd];
+        }
+        if constexpr (MC) {
+            r.c.b = v[li - stC];
+            r.c.a = v[li + oCa];
+            r.c.c = v[li + stC];
+            r.c.d = v[li + oCd];
+        }
+        return r;
+    };
+    XS xs[8];
+    if constexpr (M != (1 << A))
+        xs[KB] = load_cross(std::integral_constant<int, KB>{});
+    static_for<KB, KE>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         constexpr int tpos = 2 * k + 1;
         const int li = li0 + tpos * stA;
+        if constexpr (M != (1 << A) && k + 1 < KE)
+            xs[k + 1] = load_cross(std::integral_constant<int, (k + 1 < KE ? k + 1 : k)>{});
         int rA;
         const float pA = stencil_ct<CUB, (k > 0), true, (k < 7)>(
             k > 0 ? w[k > 0 ? k - 1 : 0] : 0.f, w[k], w[k + 1], k < 7 ? w[k < 7 ? k + 2 : 8] : 0.f,
@@ -525,22 +559,10 @@ __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__res
         } else {
             float pB = 0.f, pC = 0.f;
             int rB = -1, rC = -1;
-            if constexpr (MB) {
-                CrossSamples sm;
-                sm.b = v[li - stB];
-                sm.a = v[li + oBa];
-                sm.c = v[li + stB];
-                sm.d = v[li + oBd];
-                pB = cross_eval<CUB, true>(sm, fB, rB);
-            }
-            if constexpr (MC) {
-                CrossSamples sm;
-                sm.b = v[li - stC];
-                sm.a = v[li + oCa];
-                sm.c = v[li + stC];
-                sm.d = v[li + oCd];
-                pC = cross_eval<CUB, true>(sm, fC, rC);
-            }
+            if constexpr (MB)
+                pB = cross_eval<CUB, true>(xs[k].b, fB, rB);
+            if constexpr (MC)
+                pC = cross_eval<CUB, true>(xs[k].c, fC, rC);
             const float px = A == 0 ? pA : pB;
             const int rx = A == 0 ? rA : rB;
             const float py = A == 1 ? pA : (B == 1 ? pB : pC);
@@ -560,6 +582,27 @@ __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__res
             v[li] = c8 != 0 ? p + ((float)((int)c8 - 128) * q.two_eb) : xv[k];
         }
     });
+}
+
+// Half of a line of three-dimensional targets (sub-step 3 of the MD scheme,
+// whose lines number half the workgroup or fewer): targets 0..3 or 4..7.
+template <int TZ, int CUB, bool COMP>
+__device__ __forceinline__ void run_half_line_s1(const LineGroup &G, int l, int half, float *v,
+                                                 uint8_t *cb, const uint8_t *cl, const Geo &g,
+                                                 const QParams &q)
+{
+    const uint32_t nbc = (uint32_t)(G.cntB * G.cntC);
+    const uint32_t cell = qdiv((uint32_t)l, nbc, G.mBC);
+    const uint32_t rem = (uint32_t)l - cell * nbc;
+    const uint32_t iB = qdiv(rem, (uint32_t)G.cntC, G.mC);
+    const uint32_t iC = rem - iB * (uint32_t)G.cntC;
+    const int cB = mode_coord(G.modeB, (int)iB, 1);
+    const int cC = mode_coord(G.modeC, (int)iC, 1);
+    const int z0 = 16 * (int)cell;
+    if (half == 0)
+        do_line_s1<TZ, 2, 1, 1, CUB, COMP, 0, 4>(v, cb, cl, g, cB, cC, z0, q);
+    else
+        do_line_s1<TZ, 2, 1, 1, CUB, COMP, 4, 8>(v, cb, cl, g, cB, cC, z0, q);
 }
 
 template <int TZ, int CUB, bool COMP>
@@ -648,6 +691,12 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
         const int n2 = n1 + (ng > 2 ? G2.lines : 0);
         if (FULL && BS == 16 && S == 1) {
             if constexpr (FULL && BS == 16) {
+                if (md && sub == 3 && 2 * n0 <= NT) {
+                    // three-dimensional targets: half lines, one per thread
+                    if ((int)threadIdx.x < 2 * n0)
+                        run_half_line_s1<TZ, CUB, COMP>(G0, threadIdx.x >> 1, threadIdx.x & 1, v,
+                                                        cb, cl, g, q);
+                } else
                 for (int i = threadIdx.x; i < n2; i += NT) {
                     if (i < n0)
                         run_line_s1<TZ, CUB, COMP>(G0, i, v, cb, cl, g, q);
