@@ -21,6 +21,8 @@ extra keys of the same JSON line:
   eb_sweep  the same field at rel eb 1e-2 and 1e-4;
   pipelines the same field at rel eb 1e-3 through the throughput mode
             (TCMS1-BIT1-RRE1) and the ratio mode (Huffman + RRE4-TCMS8-RZE1);
+  forced_interp  the same field with the cubic (and the natural cubic) spline
+            forced on every level, with the interpolation kernels' times;
   front     the anisotropic 100x500x500 field with a tanh front at rel eb 1e-3
             and 1e-4, with the tuner's per-level picks;
   batch64   64 uneven fields (sides 32..384, spectra k^-2..k^-4, rel eb 1e-3):
@@ -399,6 +401,20 @@ def main():
                                profile=False)
             pipes[name] = field_summary(x, me)
         res["pipelines"] = pipes
+        # the interpolation kernels with the cubic splines forced on every level (the tuner
+        # picks the linear spline on this field), multi-dimensional scheme (Sec. 5.1.1-5.1.2)
+        forced = {}
+        for name, spline in (("cubic_md", hiz.CUBIC), ("natural_cubic_md", hiz.NATURAL)):
+            log(f"forced interpolation: {name}")
+            pp = hiz.make_params(tune=False, level_cfg=((spline, hiz.MD, 0),) * 4,
+                                 chunk=args.chunk, tile_z=args.tile_z)
+            me = measure_field(ctx, hiz, torch, xd, x, args.eb, pp, 5, 2, zbuf, ybuf, sh,
+                               profile=True)
+            fs = field_summary(x, me)
+            fs["kernels_ms"] = {k: round(v[1], 5) for k, v in me["prof"].items()
+                                if k in ("coarse", "predict_quant", "coarse_rec", "reconstruct")}
+            forced[name] = fs
+        res["forced_interp"] = forced
         del xd, zbuf, ybuf, x
         torch.cuda.empty_cache()
         log("front field 100x500x500")

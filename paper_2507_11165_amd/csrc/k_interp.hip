@@ -454,23 +454,27 @@ __device__ __forceinline__ void run_line(const LineGroup &G, int l, int S, float
     }
 }
 
-// The finest level (stride 1) inside a full tile, where 7 of every 8 targets
-// sit: the line has its full 17 points, so the eight targets, their window
-// of nine knowns and the presence of every line sample are fixed at compile
-// time. All samples are read up front at constant offsets from the line's
-// start and the eight targets run unrolled; only the cross-axis sample
-// presence (fixed per line) is a run-time choice. Arithmetic is the same as
-// in do_line, operation for operation.
+// The finest level (stride 1) inside a full tile of blocks of BS (16: the
+// method's blocks; 8: the pre-pass's even-point grid, whose stride 1 is the
+// stride-2 level), where 7 of every 8 targets sit: the line has its full
+// BS + 1 points, so its BS / 2 targets, their window of knowns and the
+// presence of every line sample are fixed at compile time. All samples are
+// read up front at constant offsets from the line's start and the targets
+// run unrolled; only the cross-axis sample presence (fixed per line) is a
+// run-time choice. Arithmetic is the same as in do_line, operation for
+// operation.
 // KB, KE: the line's targets KB..KE-1 (a half line when a sub-step has too
 // few lines to fill the workgroup), with the knowns their stencils read.
-template <int TZ, int A, int MB, int MC, int CUB, bool COMP, int KB = 0, int KE = 8>
+template <int TZ, int A, int MB, int MC, int CUB, bool COMP, int BS = 16, int KB = 0,
+          int KE = BS / 2>
 __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__restrict__ cb,
                                            const uint8_t *__restrict__ cl, const Geo &g, int x0,
                                            int y0, int z0, const QParams &q)
 {
-    static_assert(0 <= KB && KB < KE && KE <= 8, "targets of one line");
-    constexpr int JB = KB > 0 ? KB - 1 : 0, JE = KE < 8 ? KE + 1 : 8; // knowns JB..JE
-    using TS = TileShape<TZ>;
+    constexpr int NT = BS / 2; // targets of a full line
+    static_assert(0 <= KB && KB < KE && KE <= NT, "targets of one line");
+    constexpr int JB = KB > 0 ? KB - 1 : 0, JE = KE < NT ? KE + 1 : NT; // knowns JB..JE
+    using TS = TileShape<TZ, BS>;
     constexpr int B = (A == 0) ? 1 : 0;
     constexpr int C = (A == 2) ? 1 : 2;
     constexpr int stA = A == 0 ? TS::PX : (A == 1 ? TS::PZ : 1);
@@ -482,33 +486,33 @@ __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__res
     // cross-axis sample presence, fixed along the line
     const int cB = B == 0 ? x0 : y0;
     const int cC = C == 1 ? y0 : z0;
-    const int loC = C == 2 ? (cC & ~15) : 0;
-    const CrossFlags fB = cross_flags<true>(cB, 0, kSide - 1, 1);
-    const CrossFlags fC = cross_flags<true>(cC, loC, loC + 16, 1);
+    const int loC = C == 2 ? (cC & ~(BS - 1)) : 0;
+    const CrossFlags fB = cross_flags<true>(cB, 0, TS::SIDE - 1, 1);
+    const CrossFlags fC = cross_flags<true>(cC, loC, loC + BS, 1);
     const int oBa = fB.pa ? -3 * stB : -stB, oBd = fB.pd ? 3 * stB : stB;
     const int oCa = fC.pa ? -3 * stC : -stC, oCd = fC.pd ? 3 * stC : stC;
     // codes: owned lines write at a fixed step, others to the dummy slot
-    constexpr int cstep = A == 0 ? 16 * TS::OZ : (A == 1 ? TS::OZ : 1);
+    constexpr int cstep = A == 0 ? BS * TS::OZ : (A == 1 ? TS::OZ : 1);
     bool own;
     int cbase;
     if constexpr (A == 2) {
         own = x0 < g.ownx && y0 < g.owny;
-        cbase = (x0 * 16 + y0) * TS::OZ + z0;
+        cbase = (x0 * BS + y0) * TS::OZ + z0;
     } else if constexpr (A == 1) {
         own = x0 < g.ownx && z0 < g.ownz;
-        cbase = x0 * 16 * TS::OZ + z0;
+        cbase = x0 * BS * TS::OZ + z0;
     } else {
         own = y0 < g.owny && z0 < g.ownz;
         cbase = y0 * TS::OZ + z0;
     }
     const int cb0 = own ? cbase : TS::NC;
     const int cst = own ? cstep : 0;
-    float w[9];
+    float w[NT + 1];
 #pragma unroll
     for (int j = JB; j <= JE; j++)
         w[j] = vl[2 * j * stA];
-    float xv[8];
-    uint8_t cc[8];
+    float xv[NT];
+    uint8_t cc[NT];
 #pragma unroll
     for (int k = KB; k < KE; k++) {
         xv[k] = vl[(2 * k + 1) * stA];
@@ -540,7 +544,7 @@ __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__res
         }
         return r;
     };
-    XS xs[8];
+    XS xs[NT];
     if constexpr (M != (1 << A))
         xs[KB] = load_cross(std::integral_constant<int, KB>{});
     static_for<KB, KE>([&](auto kc) {
@@ -550,9 +554,9 @@ __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__res
         if constexpr (M != (1 << A) && k + 1 < KE)
             xs[k + 1] = load_cross(std::integral_constant<int, (k + 1 < KE ? k + 1 : k)>{});
         int rA;
-        const float pA = stencil_ct<CUB, (k > 0), true, (k < 7)>(
-            k > 0 ? w[k > 0 ? k - 1 : 0] : 0.f, w[k], w[k + 1], k < 7 ? w[k < 7 ? k + 2 : 8] : 0.f,
-            rA);
+        const float pA = stencil_ct<CUB, (k > 0), true, (k < NT - 1)>(
+            k > 0 ? w[k > 0 ? k - 1 : 0] : 0.f, w[k], w[k + 1],
+            k < NT - 1 ? w[k < NT - 1 ? k + 2 : NT] : 0.f, rA);
         float p;
         if constexpr (M == (1 << A)) {
             p = pA;
@@ -585,8 +589,9 @@ __device__ __forceinline__ void do_line_s1(float *__restrict__ v, uint8_t *__res
 }
 
 // Half of a line of three-dimensional targets (sub-step 3 of the MD scheme,
-// whose lines number half the workgroup or fewer): targets 0..3 or 4..7.
-template <int TZ, int CUB, bool COMP>
+// whose lines number half the workgroup or fewer): the first or second half
+// of its targets.
+template <int TZ, int CUB, bool COMP, int BS>
 __device__ __forceinline__ void run_half_line_s1(const LineGroup &G, int l, int half, float *v,
                                                  uint8_t *cb, const uint8_t *cl, const Geo &g,
                                                  const QParams &q)
@@ -598,14 +603,15 @@ __device__ __forceinline__ void run_half_line_s1(const LineGroup &G, int l, int 
     const uint32_t iC = rem - iB * (uint32_t)G.cntC;
     const int cB = mode_coord(G.modeB, (int)iB, 1);
     const int cC = mode_coord(G.modeC, (int)iC, 1);
-    const int z0 = 16 * (int)cell;
+    const int z0 = BS * (int)cell;
+    constexpr int H = BS / 4;
     if (half == 0)
-        do_line_s1<TZ, 2, 1, 1, CUB, COMP, 0, 4>(v, cb, cl, g, cB, cC, z0, q);
+        do_line_s1<TZ, 2, 1, 1, CUB, COMP, BS, 0, H>(v, cb, cl, g, cB, cC, z0, q);
     else
-        do_line_s1<TZ, 2, 1, 1, CUB, COMP, 4, 8>(v, cb, cl, g, cB, cC, z0, q);
+        do_line_s1<TZ, 2, 1, 1, CUB, COMP, BS, H, 2 * H>(v, cb, cl, g, cB, cC, z0, q);
 }
 
-template <int TZ, int CUB, bool COMP>
+template <int TZ, int CUB, bool COMP, int BS>
 __device__ __forceinline__ void run_line_s1(const LineGroup &G, int l, float *v, uint8_t *cb,
                                             const uint8_t *cl, const Geo &g, const QParams &q)
 {
@@ -617,19 +623,19 @@ __device__ __forceinline__ void run_line_s1(const LineGroup &G, int l, float *v,
     const int cB = mode_coord(G.modeB, (int)iB, 1);
     const int cC = mode_coord(G.modeC, (int)iC, 1);
     if (G.A == 2) {
-        const int z0 = 16 * (int)cell;
+        const int z0 = BS * (int)cell;
         switch (G.kind) {
-        case 0: do_line_s1<TZ, 2, 0, 0, CUB, COMP>(v, cb, cl, g, cB, cC, z0, q); break;
-        case 4: do_line_s1<TZ, 2, 1, 0, CUB, COMP>(v, cb, cl, g, cB, cC, z0, q); break;
-        case 5: do_line_s1<TZ, 2, 0, 1, CUB, COMP>(v, cb, cl, g, cB, cC, z0, q); break;
-        default: do_line_s1<TZ, 2, 1, 1, CUB, COMP>(v, cb, cl, g, cB, cC, z0, q); break;
+        case 0: do_line_s1<TZ, 2, 0, 0, CUB, COMP, BS>(v, cb, cl, g, cB, cC, z0, q); break;
+        case 4: do_line_s1<TZ, 2, 1, 0, CUB, COMP, BS>(v, cb, cl, g, cB, cC, z0, q); break;
+        case 5: do_line_s1<TZ, 2, 0, 1, CUB, COMP, BS>(v, cb, cl, g, cB, cC, z0, q); break;
+        default: do_line_s1<TZ, 2, 1, 1, CUB, COMP, BS>(v, cb, cl, g, cB, cC, z0, q); break;
         }
     } else if (G.A == 1) {
-        do_line_s1<TZ, 1, 0, 0, CUB, COMP>(v, cb, cl, g, cB, 0, cC, q);
+        do_line_s1<TZ, 1, 0, 0, CUB, COMP, BS>(v, cb, cl, g, cB, 0, cC, q);
     } else if (G.kind == 3) {
-        do_line_s1<TZ, 0, 1, 0, CUB, COMP>(v, cb, cl, g, 0, cB, cC, q);
+        do_line_s1<TZ, 0, 1, 0, CUB, COMP, BS>(v, cb, cl, g, 0, cB, cC, q);
     } else {
-        do_line_s1<TZ, 0, 0, 0, CUB, COMP>(v, cb, cl, g, 0, cB, cC, q);
+        do_line_s1<TZ, 0, 0, 0, CUB, COMP, BS>(v, cb, cl, g, 0, cB, cC, q);
     }
 }
 
@@ -689,21 +695,21 @@ __device__ __forceinline__ void level_lines(float *v, uint8_t *cb, const uint8_t
         const int n0 = G0.lines;
         const int n1 = n0 + (ng > 1 ? G1.lines : 0);
         const int n2 = n1 + (ng > 2 ? G2.lines : 0);
-        if (FULL && BS == 16 && S == 1) {
-            if constexpr (FULL && BS == 16) {
+        if (FULL && S == 1) {
+            if constexpr (FULL) {
                 if (md && sub == 3 && 2 * n0 <= NT) {
                     // three-dimensional targets: half lines, one per thread
                     if ((int)threadIdx.x < 2 * n0)
-                        run_half_line_s1<TZ, CUB, COMP>(G0, threadIdx.x >> 1, threadIdx.x & 1, v,
-                                                        cb, cl, g, q);
+                        run_half_line_s1<TZ, CUB, COMP, BS>(G0, threadIdx.x >> 1, threadIdx.x & 1,
+                                                            v, cb, cl, g, q);
                 } else
                 for (int i = threadIdx.x; i < n2; i += NT) {
                     if (i < n0)
-                        run_line_s1<TZ, CUB, COMP>(G0, i, v, cb, cl, g, q);
+                        run_line_s1<TZ, CUB, COMP, BS>(G0, i, v, cb, cl, g, q);
                     else if (i < n1)
-                        run_line_s1<TZ, CUB, COMP>(G1, i - n0, v, cb, cl, g, q);
+                        run_line_s1<TZ, CUB, COMP, BS>(G1, i - n0, v, cb, cl, g, q);
                     else
-                        run_line_s1<TZ, CUB, COMP>(G2, i - n1, v, cb, cl, g, q);
+                        run_line_s1<TZ, CUB, COMP, BS>(G2, i - n1, v, cb, cl, g, q);
                 }
             }
         } else {
