@@ -411,7 +411,8 @@ def main():
             me = measure_field(ctx, hiz, torch, xd, x, args.eb, pp, 5, 2, zbuf, ybuf, sh,
                                profile=True)
             fs = field_summary(x, me)
-            fs["kernels_ms"] = {k: round(v[1], 5) for k, v in me["prof"].items()
+            # mean launch time of each interpolation kernel (total / launches)
+            fs["kernels_ms"] = {k: round(v[1] / max(v[0], 1), 5) for k, v in me["prof"].items()
                                 if k in ("coarse", "predict_quant", "coarse_rec", "reconstruct")}
             forced[name] = fs
         res["forced_interp"] = forced
