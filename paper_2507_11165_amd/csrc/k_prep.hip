@@ -87,13 +87,14 @@ __global__ __launch_bounds__(256) void k_minmax(const Job *__restrict__ jobs, in
         const bool vec = ((reinterpret_cast<uintptr_t>(f) & 15u) == 0) && (hi - lo == kMmUnit);
         if (vec) {
             // all 16 loads of a thread in flight before any is used: one
-            // memory round trip per unit
+            // memory round trip per unit; streamed (the field is larger than
+            // the caches, so nothing of it would be found there later)
             HIZ_GLOBAL const float *fb = f + lo;
             constexpr int K = (int)(kMmUnit / 4 / 256);
             float4 q4[K];
 #pragma unroll
             for (int k = 0; k < K; k++)
-                q4[k] = gload_f4(fb + 4 * (k * 256 + t));
+                q4[k] = gload_f4_nt(fb + 4 * (k * 256 + t));
 #pragma unroll
             for (int k = 0; k < K; k++) {
                 const float4 q = q4[k];
