@@ -282,26 +282,12 @@ __device__ __forceinline__ uint4 gload_u4(HIZ_GLOBAL const uint8_t *p)
     const hiz_u4v v = *(HIZ_GLOBAL const hiz_u4v *)p;
     return make_uint4(v.x, v.y, v.z, v.w);
 }
-// Streaming variants for data read or written once per call (no reuse for
-// the caches to keep; marked non-temporal).
+// A streamed load for data read once per call and larger than the caches
+// (marked non-temporal).
 __device__ __forceinline__ float4 gload_f4_nt(HIZ_GLOBAL const float *p)
 {
     const hiz_f4v v = __builtin_nontemporal_load((HIZ_GLOBAL const hiz_f4v *)p);
     return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ uint4 gload_u4_nt(HIZ_GLOBAL const uint8_t *p)
-{
-    const hiz_u4v v = __builtin_nontemporal_load((HIZ_GLOBAL const hiz_u4v *)p);
-    return make_uint4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void gstore_f4_nt(HIZ_GLOBAL float *p, const float4 &v)
-{
-    hiz_f4v w;
-    w.x = v.x;
-    w.y = v.y;
-    w.z = v.z;
-    w.w = v.w;
-    __builtin_nontemporal_store(w, (HIZ_GLOBAL hiz_f4v *)p);
 }
 __device__ __forceinline__ void gstore_f4(HIZ_GLOBAL float *p, const float4 &v)
 {

@@ -1557,10 +1557,9 @@ __global__ __launch_bounds__(256, 3) void k_reconstruct(const Job *__restrict__ 
                 const int w = i % (4 * TZ), r = i / (4 * TZ);
                 const int y = r % 16, x = r / 16;
                 if (x < g.ownx && y < g.owny) {
-                    // the output's last write: streamed
                     const float *vp = v + x * TS::PX + y * TS::PZ + 4 * w;
-                    gstore_f4_nt(gmem(J.out) + base + (uint64_t)x * sx + (uint64_t)y * dz + 4 * w,
-                                 make_float4(vp[0], vp[1], vp[2], vp[3]));
+                    gstore_f4(gmem(J.out) + base + (uint64_t)x * sx + (uint64_t)y * dz + 4 * w,
+                              make_float4(vp[0], vp[1], vp[2], vp[3]));
                 }
             }
         } else {
