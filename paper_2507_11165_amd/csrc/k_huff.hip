@@ -332,11 +332,13 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
     __shared__ uint8_t len[256];
     __shared__ uint32_t s_words[kGroupChunks], s_zeros[kGroupChunks];
     __shared__ uint32_t s_gid;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    // wave and group indices read back as uniform values, so that the job
+    // lookup and the job's fields go through scalar loads
+    const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
     if (t == 0)
         s_gid = atomicAdd(&cnt->enc_next, 1u);
     __syncthreads();
-    const uint64_t gid = s_gid;
+    const uint64_t gid = __builtin_amdgcn_readfirstlane(s_gid);
     if (gid >= total)
         return;
     const Job &J = jobs[find_job<WK_GROUP>(jobs, njobs, gid)];
@@ -438,7 +440,9 @@ __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, 
     // per wave: (code, length) of every symbol, and the pack buffer
     __shared__ uint2 s_cl[kEncWaves][256];
     __shared__ uint32_t s_buf[kEncWaves][kEncBuf];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // uniform wave index: the chunk loop, the job lookup and the job's fields
+    // stay scalar
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     uint2 *cl = s_cl[wv];
     uint32_t *buf = s_buf[wv];
     for (int k = lane; k < kEncBuf; k += 64)
