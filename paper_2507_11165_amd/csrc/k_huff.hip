@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
     if (t == 0)
         s_gid = atomicAdd(&cnt->enc_next, 1u);
     __syncthreads();
-    const uint64_t gid = __builtin_amdgcn_readfirstlane(s_gid);
+    const uint64_t gid = (uint32_t)__builtin_amdgcn_readfirstlane(s_gid);
     if (gid >= total)
         return;
     const Job &J = jobs[find_job<WK_GROUP>(jobs, njobs, gid)];
@@ -434,7 +434,22 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
     }
 }
 
-__global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, int njobs,
+// A wave-uniform 64-bit value read back from the first lane, so that the
+// compiler keeps it in scalar registers. The builtin returns a signed int:
+// each half goes back to uint32_t before widening, or a low half at or above
+// 2^31 would be sign-extended over the high half.
+__device__ __forceinline__ uint64_t uni64(uint64_t u)
+{
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+    return ((uint64_t)hi << 32) | lo;
+}
+template <typename T> __device__ __forceinline__ T *uni_ptr(T *p)
+{
+    return reinterpret_cast<T *>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+
+__global__ __launch_bounds__(256, 5) void k_enc_pack(const Job *__restrict__ jobs, int njobs,
                                                   uint64_t total)
 {
     // per wave: (code, length) of every symbol, and the pack buffer
@@ -447,48 +462,68 @@ __global__ __launch_bounds__(256) void k_enc_pack(const Job *__restrict__ jobs, 
     uint32_t *buf = s_buf[wv];
     for (int k = lane; k < kEncBuf; k += 64)
         buf[k] = 0;
+    // values of the current job, loaded again only when the wave moves on to
+    // another job
     int cur = -1;
+    bool skip = false, cr = false, outl = false;
+    int ib = 0;
+    uint64_t o_idx = 0, o_val = 0, pay_words_cap = 0, cap = 0;
+    HIZ_GLOBAL uint8_t *stream = nullptr;
+    HIZ_GLOBAL uint32_t *payload = nullptr;
+    HIZ_GLOBAL const float *field = nullptr;
     for (uint64_t id = (uint64_t)blockIdx.x * kEncWaves + wv; id < total;
          id += (uint64_t)gridDim.x * kEncWaves) {
         const int ji = find_job<WK_CHUNK>(jobs, njobs, id);
         const Job &J = jobs[ji];
-        FieldState *st = J.st;
-        if (st->flags & (ST_CONST | ST_NONFINITE))
-            continue;
         if (ji != cur) {
+            FieldState *st = J.st;
+            cur = ji;
+            skip = (st->flags & (ST_CONST | ST_NONFINITE)) != 0;
+            if (skip)
+                continue;
             for (int k = lane; k < 256; k += 64)
                 cl[k] = make_uint2(st->cb_code[k], st->cb_len[k]);
-            cur = ji;
+            cap = uni64(J.cap);
+            stream = uni_ptr(gmem(J.stream));
+            field = uni_ptr(gmem(J.field));
+            // the payload goes to the stream, or (ratio mode) to the workspace for the last stages
+            cr = __builtin_amdgcn_readfirstlane((int)(J.pipe == PIPE_CR)) != 0;
+            const uint64_t off_payload = uni64(st->off_payload);
+            payload = cr ? reinterpret_cast<HIZ_GLOBAL uint32_t *>(gmem(J.hpay))
+                         : reinterpret_cast<HIZ_GLOBAL uint32_t *>(stream + off_payload);
+            payload = uni_ptr(payload);
+            pay_words_cap =
+                cr ? uni64(J.hpay_cap) / 4 : (cap > off_payload ? (cap - off_payload) / 4 : 0);
+            // outliers here only when these codes are in row-major order
+            outl = __builtin_amdgcn_readfirstlane((int)!J.reorder) != 0;
+            o_idx = uni64(st->off_oidx);
+            o_val = uni64(st->off_oval);
+            ib = __builtin_amdgcn_readfirstlane((int)J.idx_bytes);
             wave_sync_lds();
         }
+        if (skip)
+            continue;
         const uint64_t ck = id - J.chunk_begin;
         const uint64_t c0 = ck << J.log2_chunk;
         const int clen = (int)(min(c0 + J.chunk, J.N) - c0);
         HIZ_GLOBAL const uint8_t *src = gmem(J.seq) + c0;
-        HIZ_GLOBAL uint8_t *stream = gmem(J.stream);
-        HIZ_GLOBAL const float *field = gmem(J.field);
+        // a chunk of exactly one segment: its codes (16 per lane) are loaded
+        // together with the chunk's offsets
+        const bool one = clen == kEncSeg;
+        uint4 pre = make_uint4(0u, 0u, 0u, 0u);
+        if (one)
+            pre = gload_u4(src + 16 * lane);
         const uint64_t wbase = gmem(J.woff)[ck];
         uint64_t zpos0 = gmem(J.zoff)[ck];
-        const uint64_t cap = J.cap;
-        // the payload goes to the stream, or (ratio mode) to the workspace for the last stages
-        const bool cr = J.pipe == PIPE_CR;
-        HIZ_GLOBAL uint32_t *payload =
-            cr ? reinterpret_cast<HIZ_GLOBAL uint32_t *>(gmem(J.hpay))
-               : reinterpret_cast<HIZ_GLOBAL uint32_t *>(stream + st->off_payload);
-        const uint64_t pay_words_cap =
-            cr ? J.hpay_cap / 4 : (cap > st->off_payload ? (cap - st->off_payload) / 4 : 0);
-        // outliers here only when these codes are in row-major order
-        const bool outl = !J.reorder;
-        const uint64_t o_idx = st->off_oidx, o_val = st->off_oval;
-        const int ib = J.idx_bytes;
         uint64_t sb = 0; // chunk-relative bit at the segment start
         for (int sg = 0; sg * kEncSeg < clen; sg++) {
             const int sl = min(kEncSeg, clen - sg * kEncSeg);
             const int P = (sl + 63) / 64;
             const int n = max(0, min(P, sl - lane * P));
             const uint64_t gfirst = c0 + (uint64_t)sg * kEncSeg + (uint64_t)lane * P;
-            uint32_t r[4];
-            load_lane_codes(src + sg * kEncSeg + lane * P, P, n, r);
+            uint32_t r[4] = {pre.x, pre.y, pre.z, pre.w};
+            if (!one)
+                load_lane_codes(src + sg * kEncSeg + lane * P, P, n, r);
             // every symbol's (code, length) at once; lengths of absent
             // symbols (past n) count zero
             uint2 e[16];

@@ -858,9 +858,12 @@ __device__ __forceinline__ uint64_t claim_tile(TileQueue &q, uint64_t *slot, int
         slot[it & 1] = next_tile(q);
     lds_barrier();
     // the same for every lane: job lookups and job fields go to scalar loads
+    // (the builtin returns a signed int: both halves go back to uint32_t
+    // before widening, so that the low half is never sign-extended)
     const uint64_t u = slot[it & 1];
-    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32)) << 32) |
-           __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // ---------------------------------------------------------------------------
