@@ -58,6 +58,7 @@ __global__ __launch_bounds__(256) void k_codebook(const Job *__restrict__ jobs, 
     const Job &J = jobs[blockIdx.x];
     FieldState *st = J.st;
     __shared__ uint64_t cnt[256];
+    __shared__ uint64_t key[256];
     __shared__ uint64_t w[512];
     __shared__ int16_t par[512];
     __shared__ uint8_t leafsym[256];
@@ -118,12 +119,17 @@ __global__ __launch_bounds__(256) void k_codebook(const Job *__restrict__ jobs, 
     for (;;) {
         __syncthreads();
         const uint64_t c = cnt[t];
+        // (count, symbol) as one key, 0 for an absent symbol (counts stay below
+        // 2^56); the rank of a present symbol is the number of present keys
+        // below its own, and key - 1 wraps an absent one past every other key
+        key[t] = c ? (c << 8) | (uint64_t)t : 0;
+        __syncthreads();
         int rank = 0;
         if (c) {
-            for (int j = 0; j < 256; j++) {
-                const uint64_t cj = cnt[j];
-                rank += (cj != 0) & ((cj < c) | ((cj == c) & (j < t)));
-            }
+            const uint64_t km = key[t] - 1;
+#pragma unroll 8
+            for (int j = 0; j < 256; j++)
+                rank += (key[j] - 1) < km;
         }
         const int n = __syncthreads_count(c != 0);
         if (c) {
