@@ -359,31 +359,44 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
     // chunks of exactly one segment (kEncSeg codes, 16 per lane): the next
     // chunk's codes are loaded while this one is sized
     const bool seg1 = J.chunk == (uint32_t)kEncSeg;
-    const int kw = kGroupChunks / kEncWaves;
+    constexpr int kw = kGroupChunks / kEncWaves;
     HIZ_GLOBAL const uint8_t *seq = gmem(J.seq);
-    uint4 nxt = make_uint4(0u, 0u, 0u, 0u);
-    auto full_chunk = [&](int lc) {
-        return lc < nc && ((cfirst + lc + 1) << J.log2_chunk) <= J.N;
-    };
-    if (seg1 && full_chunk(wv * kw))
-        nxt = gload_u4(seq + ((cfirst + wv * kw) << J.log2_chunk) + 16 * lane);
-    for (int k = 0; k < kw; k++) {
-        const int lc = wv * kw + k;
-        if (lc >= nc)
-            break;
-        const uint64_t ck = cfirst + lc;
-        const uint64_t c0 = ck << J.log2_chunk;
-        const int clen = (int)(min(c0 + J.chunk, J.N) - c0);
-        uint64_t bits = 0;
-        uint32_t zeros = 0;
-        if (seg1 && clen == kEncSeg) {
-            uint32_t r[4] = {nxt.x, nxt.y, nxt.z, nxt.w}, b, z;
-            if (k + 1 < kw && full_chunk(lc + 1))
-                nxt = gload_u4(seq + ((ck + 1) << J.log2_chunk) + 16 * lane);
+    if (seg1 && nc == kGroupChunks && ((cfirst + kGroupChunks) << J.log2_chunk) <= J.N) {
+        // a whole group of one-segment chunks: the wave's kw chunks are sized
+        // in an unrolled sequence with kDepth loads in flight (one load per
+        // chunk would leave each chunk waiting out a full memory latency).
+        // A lane's bits (<= 16 x 32) and outliers (<= 16) share one word, and
+        // so do the chunk's sums (<= 2^15 bits, <= 2^10 outliers).
+        constexpr int kDepth = 4;
+        HIZ_GLOBAL const uint8_t *p = seq + ((cfirst + wv * kw) << J.log2_chunk) + 16 * lane;
+        uint4 q[kDepth];
+#pragma unroll
+        for (int k = 0; k < kDepth; k++)
+            q[k] = gload_u4(p + k * kEncSeg);
+#pragma unroll
+        for (int k = 0; k < kw; k++) {
+            const uint4 v = q[k % kDepth];
+            if (k + kDepth < kw)
+                q[k % kDepth] = gload_u4(p + (k + kDepth) * kEncSeg);
+            uint32_t r[4] = {v.x, v.y, v.z, v.w}, b, z;
             lane_sizes(r, 16, len, b, z);
-            bits = b;
-            zeros = z;
-        } else {
+            uint32_t bz = (z << 16) | b;
+            for (int o = 32; o > 0; o >>= 1)
+                bz += (uint32_t)__shfl_xor((int)bz, o, 64);
+            if (lane == 0) {
+                s_words[wv * kw + k] = ((bz & 0xFFFFu) + 31) >> 5;
+                s_zeros[wv * kw + k] = bz >> 16;
+            }
+        }
+    } else {
+        for (int k = 0; k < kw; k++) {
+            const int lc = wv * kw + k;
+            if (lc >= nc)
+                break;
+            const uint64_t c0 = (cfirst + lc) << J.log2_chunk;
+            const int clen = (int)(min(c0 + J.chunk, J.N) - c0);
+            uint64_t bits = 0;
+            uint32_t zeros = 0;
             for (int sg = 0; sg * kEncSeg < clen; sg++) {
                 const int sl = min(kEncSeg, clen - sg * kEncSeg);
                 const int P = (sl + 63) / 64;
@@ -394,14 +407,14 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
                 bits += b;
                 zeros += z;
             }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            bits += shfl64(bits, lane ^ o);
-            zeros += (uint32_t)__shfl_xor((int)zeros, o, 64);
-        }
-        if (lane == 0) {
-            s_words[lc] = (uint32_t)((bits + 31) >> 5);
-            s_zeros[lc] = zeros;
+            for (int o = 32; o > 0; o >>= 1) {
+                bits += shfl64(bits, lane ^ o);
+                zeros += (uint32_t)__shfl_xor((int)zeros, o, 64);
+            }
+            if (lane == 0) {
+                s_words[lc] = (uint32_t)((bits + 31) >> 5);
+                s_zeros[lc] = zeros;
+            }
         }
     }
     __syncthreads();
