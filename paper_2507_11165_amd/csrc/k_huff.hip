@@ -316,20 +316,33 @@ __device__ inline uint32_t code_at(const uint32_t r[4], int k)
     return (w >> (8 * (k & 3))) & 255u;
 }
 
+// Outlier codes (zero bytes) among the first n codes (n <= 16) of r, four
+// at a time: after adding 0x7F to each byte's low seven bits, a byte's top bit
+// is clear in (sum | byte) only when the byte is zero.
+__device__ inline uint32_t zero_codes(const uint32_t r[4], int n)
+{
+    uint32_t z = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t x = r[j];
+        const uint32_t m = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
+        const int nb = n - 4 * j;
+        const uint32_t valid = nb >= 4 ? 0xFFFFFFFFu : nb <= 0 ? 0u : (1u << (8 * nb)) - 1u;
+        z += __builtin_popcount(m & valid);
+    }
+    return z;
+}
+
 // Bits and outliers of one lane's share of a segment.
 __device__ inline void lane_sizes(const uint32_t r[4], int n, const uint8_t *len, uint32_t &bits,
                                   uint32_t &zeros)
 {
     bits = 0;
-    zeros = 0;
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        if (k < n) {
-            const uint32_t c = code_at(r, k);
-            bits += len[c];
-            zeros += (c == 0);
-        }
-    }
+    for (int k = 0; k < 16; k++)
+        if (k < n)
+            bits += len[code_at(r, k)];
+    zeros = zero_codes(r, n);
 }
 
 __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs, int njobs,
@@ -692,8 +705,9 @@ void launch_init_decompress(const Job *d_jobs, int njobs, uint64_t max_blocks, C
 // Decoder tables from the stored code lengths: canonical codes, a direct
 // lookup table of up to two codes within kLutBits bits, and per-length ranges
 // for longer codes. The lookup table is built by kDecTableParts workgroups
-// per field, one slice each; the first also writes the per-length tables.
-constexpr int kDecTableParts = 8;
+// per field, one slice each (one entry per thread); the first also writes
+// the per-length tables.
+constexpr int kDecTableParts = 32;
 
 __global__ __launch_bounds__(256) void k_dec_tables(const Job *__restrict__ jobs, int njobs)
 {
