@@ -402,22 +402,38 @@ void launch_tune(const Job *d_jobs, int njobs, uint64_t total, hipStream_t s)
 
 // Per-level argmin (ties to the lower candidate), or the forced/default
 // configuration when the tuner is off or no full block exists.
-__global__ void k_tune_pick(const Job *__restrict__ jobs, int njobs)
+// One wave per field: each lane loads one candidate's error of every level at
+// once, and a wave argmin picks the smallest error, the lower candidate on
+// equal errors (the first in candidate order).
+__global__ __launch_bounds__(64) void k_tune_pick(const Job *__restrict__ jobs, int njobs)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= njobs)
-        return;
-    const Job &J = jobs[j];
+    static_assert(kCands <= 64, "one lane per candidate");
+    const Job &J = jobs[blockIdx.x];
     FieldState *st = J.st;
+    const int lane = threadIdx.x;
+    const bool measured = J.tune && J.n_samples > 0;
+    uint64_t err[kLevels];
+#pragma unroll
+    for (int l = 0; l < kLevels; l++)
+        err[l] = measured && lane < kCands ? st->tune_err[l][lane] : ~0ull;
+#pragma unroll
     for (int l = 0; l < kLevels; l++) {
+        uint64_t e = err[l];
+        int c = lane;
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t e2 = shfl64(e, lane ^ o);
+            const int c2 = __shfl_xor(c, o, 64);
+            if (e2 < e || (e2 == e && c2 < c)) {
+                e = e2;
+                c = c2;
+            }
+        }
+        if (lane != 0)
+            continue;
         uint8_t sp, sc, pm;
-        if (J.tune && J.n_samples > 0) {
-            int best = 0;
-            for (int c = 1; c < kCands; c++)
-                if (st->tune_err[l][c] < st->tune_err[l][best])
-                    best = c;
-            int r = best % 7;
-            sp = (uint8_t)(best / 7);
+        if (measured) {
+            const int r = c % 7;
+            sp = (uint8_t)(c / 7);
             sc = (uint8_t)(r == 0 ? 0 : 1);
             pm = (uint8_t)(r == 0 ? 0 : r - 1);
         } else if (J.tune) {
@@ -437,7 +453,7 @@ __global__ void k_tune_pick(const Job *__restrict__ jobs, int njobs)
 
 void launch_tune_pick(const Job *d_jobs, int njobs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tune_pick, dim3((njobs + 63) / 64), dim3(64), 0, s, d_jobs, njobs);
+    hipLaunchKernelGGL(k_tune_pick, dim3(njobs), dim3(64), 0, s, d_jobs, njobs);
 }
 
 // ---------------------------------------------------------------------------
