@@ -513,8 +513,11 @@ __global__ __launch_bounds__(256, 5) void k_enc_pack(const Job *__restrict__ job
             skip = (st->flags & (ST_CONST | ST_NONFINITE)) != 0;
             if (skip)
                 continue;
-            for (int k = lane; k < 256; k += 64)
-                cl[k] = make_uint2(st->cb_code[k], st->cb_len[k]);
+            // codes left-justified in 32 bits (a symbol without a code: 0)
+            for (int k = lane; k < 256; k += 64) {
+                const uint32_t L = st->cb_len[k];
+                cl[k] = make_uint2(L ? st->cb_code[k] << (32 - L) : 0u, L);
+            }
             cap = uni64(J.cap);
             stream = uni_ptr(gmem(J.stream));
             field = uni_ptr(gmem(J.field));
@@ -565,7 +568,7 @@ __global__ __launch_bounds__(256, 5) void k_enc_pack(const Job *__restrict__ job
                 const uint32_t c = code_at(r, k);
                 e[k] = cl[c];
                 if (k >= n)
-                    e[k].y = 0;
+                    e[k] = make_uint2(0u, 0u);
             }
 #pragma unroll
             for (int k = 0; k < 16; k++) {
@@ -580,18 +583,19 @@ __global__ __launch_bounds__(256, 5) void k_enc_pack(const Job *__restrict__ job
             // bit of this lane's first code, relative to the buffer's word 0
             uint32_t p = (uint32_t)(sb & 31) + (ib_incl - mb);
             // each code is OR-ed into the (one or two) words it covers; codes
-            // are independent of one another
+            // are independent of one another. A left-justified code shifted
+            // right by its bit offset in the word fills that word; the bits
+            // shifted out (the funnel shift of code:0) start the next one. An
+            // absent symbol ORs zero.
 #pragma unroll
             for (int k = 0; k < 16; k++) {
-                const uint32_t L = e[k].y;
-                if (L) {
-                    const uint32_t w = p >> 5, sh = p & 31;
-                    const uint64_t v = (uint64_t)e[k].x << (64 - sh - L);
-                    atomicOr(&buf[w], (uint32_t)(v >> 32));
-                    if ((uint32_t)v)
-                        atomicOr(&buf[w + 1], (uint32_t)v);
-                }
-                p += L;
+                const uint32_t cL = e[k].x, sh = p & 31;
+                uint32_t *wp = buf + (p >> 5);
+                atomicOr(wp, cL >> sh);
+                const uint32_t lo = __builtin_amdgcn_alignbit(cL, 0u, sh);
+                if (lo)
+                    atomicOr(wp + 1, lo);
+                p += e[k].y;
             }
             if (outl && mz) {
                 uint64_t zpos = zpos0 + (iz_incl - mz);
