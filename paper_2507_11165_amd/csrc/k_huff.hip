@@ -575,10 +575,12 @@ __global__ __launch_bounds__(256, 5) void k_enc_pack(const Job *__restrict__ job
                 mb += e[k].y;
                 mz += (k < n) & (code_at(r, k) == 0);
             }
-            const uint32_t ib_incl = wave_incl_scan(mb);
-            const uint32_t iz_incl = wave_incl_scan(mz);
-            const uint32_t seg_bits = (uint32_t)__shfl((int)ib_incl, 63, 64);
-            const uint32_t seg_zero = (uint32_t)__shfl((int)iz_incl, 63, 64);
+            // one scan for both: a lane's bits (<= 16 x 32) and outliers (<= 16)
+            // share a word, and so do the segment's sums (<= 2^15, <= 2^10)
+            const uint32_t incl = wave_incl_scan((mz << 16) | mb);
+            const uint32_t ib_incl = incl & 0xFFFFu, iz_incl = incl >> 16;
+            const uint32_t seg = (uint32_t)__shfl((int)incl, 63, 64);
+            const uint32_t seg_bits = seg & 0xFFFFu, seg_zero = seg >> 16;
             const uint64_t wseg = sb >> 5;
             // bit of this lane's first code, relative to the buffer's word 0
             uint32_t p = (uint32_t)(sb & 31) + (ib_incl - mb);
