@@ -466,6 +466,22 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
     }
 }
 
+// Inclusive scan over the wave with DPP moves: shifts by 1, 2, 4, 8 lanes
+// within each row of 16 (zeros shifted in), then the last lane of row 0 (2)
+// added to row 1 (3), then lane 31 to rows 2 and 3. No LDS round trips.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v)
+{
+    constexpr int kRowShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 1, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 2, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 4, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 8, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kBcast15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kBcast31, 0xc, 0xf, false);
+    return (uint32_t)x;
+}
+
 // A wave-uniform 64-bit value read back from the first lane, so that the
 // compiler keeps it in scalar registers. The builtin returns a signed int:
 // each half goes back to uint32_t before widening, or a low half at or above
@@ -577,9 +593,9 @@ __global__ __launch_bounds__(256, 5) void k_enc_pack(const Job *__restrict__ job
             }
             // one scan for both: a lane's bits (<= 16 x 32) and outliers (<= 16)
             // share a word, and so do the segment's sums (<= 2^15, <= 2^10)
-            const uint32_t incl = wave_incl_scan((mz << 16) | mb);
+            const uint32_t incl = wave_incl_scan_dpp((mz << 16) | mb);
             const uint32_t ib_incl = incl & 0xFFFFu, iz_incl = incl >> 16;
-            const uint32_t seg = (uint32_t)__shfl((int)incl, 63, 64);
+            const uint32_t seg = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
             const uint32_t seg_bits = seg & 0xFFFFu, seg_zero = seg >> 16;
             const uint64_t wseg = sb >> 5;
             // bit of this lane's first code, relative to the buffer's word 0
