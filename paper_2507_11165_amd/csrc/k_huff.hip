@@ -333,6 +333,22 @@ __device__ inline uint32_t zero_codes(const uint32_t r[4], int n)
     return z;
 }
 
+// Inclusive scan over the wave with DPP moves: shifts by 1, 2, 4, 8 lanes
+// within each row of 16 (zeros shifted in), then the last lane of row 0 (2)
+// added to row 1 (3), then lane 31 to rows 2 and 3. No LDS round trips.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v)
+{
+    constexpr int kRowShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 1, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 2, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 4, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 8, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kBcast15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kBcast31, 0xc, 0xf, false);
+    return (uint32_t)x;
+}
+
 // Bits and outliers of one lane's share of a segment.
 __device__ inline void lane_sizes(const uint32_t r[4], int n, const uint8_t *len, uint32_t &bits,
                                   uint32_t &zeros)
@@ -393,9 +409,8 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
                 q[k % kDepth] = gload_u4(p + (k + kDepth) * kEncSeg);
             uint32_t r[4] = {v.x, v.y, v.z, v.w}, b, z;
             lane_sizes(r, 16, len, b, z);
-            uint32_t bz = (z << 16) | b;
-            for (int o = 32; o > 0; o >>= 1)
-                bz += (uint32_t)__shfl_xor((int)bz, o, 64);
+            const uint32_t bz =
+                (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp((z << 16) | b), 63);
             if (lane == 0) {
                 s_words[wv * kw + k] = ((bz & 0xFFFFu) + 31) >> 5;
                 s_zeros[wv * kw + k] = bz >> 16;
@@ -464,22 +479,6 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
         if (zbase + gz != st->n_out)
             atomicOr(&st->flags, (uint32_t)ST_CORRUPT);
     }
-}
-
-// Inclusive scan over the wave with DPP moves: shifts by 1, 2, 4, 8 lanes
-// within each row of 16 (zeros shifted in), then the last lane of row 0 (2)
-// added to row 1 (3), then lane 31 to rows 2 and 3. No LDS round trips.
-__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v)
-{
-    constexpr int kRowShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143;
-    int x = (int)v;
-    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 1, 0xf, 0xf, false);
-    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 2, 0xf, 0xf, false);
-    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 4, 0xf, 0xf, false);
-    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 8, 0xf, 0xf, false);
-    x += __builtin_amdgcn_update_dpp(0, x, kBcast15, 0xa, 0xf, false);
-    x += __builtin_amdgcn_update_dpp(0, x, kBcast31, 0xc, 0xf, false);
-    return (uint32_t)x;
 }
 
 // A wave-uniform 64-bit value read back from the first lane, so that the
