@@ -450,8 +450,11 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
         return;
     const uint64_t w = lane < nc ? s_words[lane] : 0;
     const uint64_t z = lane < nc ? s_zeros[lane] : 0;
-    const uint64_t wi = wave_incl_scan64(w), zi = wave_incl_scan64(z);
-    const uint64_t gw = shfl64(wi, 63), gz = shfl64(zi, 63);
+    // a group's words and outliers stay below 2^22 (chunks of at most 2^16
+    // codes): 32-bit DPP scans
+    const uint64_t wi = wave_incl_scan_dpp((uint32_t)w), zi = wave_incl_scan_dpp((uint32_t)z);
+    const uint64_t gw = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)wi, 63);
+    const uint64_t gz = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)zi, 63);
     const uint64_t wbase = lookback(J.lb_a, g, gw);
     const uint64_t zbase = lookback(J.lb_b, g, gz);
     const uint64_t cap = J.cap;
