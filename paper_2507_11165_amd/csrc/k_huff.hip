@@ -385,8 +385,7 @@ __global__ __launch_bounds__(256) void k_enc_sizes(const Job *__restrict__ jobs,
     const uint64_t g = gid - J.group_begin;
     const uint64_t cfirst = g * kGroupChunks;
     const int nc = (int)min<uint64_t>(kGroupChunks, J.n_chunks - cfirst);
-    // chunks of exactly one segment (kEncSeg codes, 16 per lane): the next
-    // chunk's codes are loaded while this one is sized
+    // chunks of exactly one segment (kEncSeg codes, 16 per lane)
     const bool seg1 = J.chunk == (uint32_t)kEncSeg;
     constexpr int kw = kGroupChunks / kEncWaves;
     HIZ_GLOBAL const uint8_t *seq = gmem(J.seq);
